@@ -1,0 +1,162 @@
+/*
+ * sfseg.h -- C ABI of the MI355X (gfx950) SFSeg power-iteration library.
+ *
+ * Burceanu & Leordeanu, "A 3D Convolutional Approach to Spectral Object
+ * Segmentation in Space and Time" (IJCAI 2020, arXiv 1907.02731).
+ *
+ * The library computes the principal eigenvector of the adjacency matrix M of
+ * a video's space-time pixel graph (Sec. 3) by power iteration (Eq. (4)
+ * followed by the normalisation of Eq. (8)), with M never formed: every step
+ * applies M as three separable 3D Gaussian filterings of the T x H x W volume
+ * fused with the element-wise terms of Eq. (7).  Node i = (t, y, x) and
+ *
+ *     w_i  = S_i^p                         (0^p = 0 for p > 0; p = 0 gives w = 1)
+ *     G(d) = exp(-dt^2/(2 sigma_t^2) - (dy^2 + dx^2)/(2 sigma_s^2)),
+ *            box |dt| <= r_t, |dy|, |dx| <= r_s, zero outside       (Eq. (1))
+ *     M_ij = w_i w_j [1 - alpha (F_i - F_j)^2] G(j - i),
+ *            neighbours outside the volume do not exist            (Eq. (2))
+ *
+ * Conventions shared by every entry point:
+ *  - Volumes are contiguous T x H x W arrays, row-major, W fastest; voxel
+ *    (t, y, x) is element (t * H + y) * W + x.
+ *  - Every array pointer is a DEVICE pointer (for example a torch tensor's
+ *    data_ptr()) on the device that was current when the context was created.
+ *    Arrays crossing the ABI are float32; the storage precision inside the
+ *    library is chosen by sfseg_config.storage.
+ *  - Work is ordered on the context's stream.  The host blocks only where an
+ *    entry point says so.  A context is not thread-safe.
+ *  - Return value: SFSEG_OK (0) or a negative sfseg_status.  Arguments are
+ *    validated before any device work; sfseg_last_error() then holds a
+ *    message for the calling thread.  No C++ exception crosses the ABI.
+ */
+#ifndef SFSEG_H
+#define SFSEG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SFSEG_VERSION_MAJOR 0
+#define SFSEG_VERSION_MINOR 1
+
+/* Largest radii the compiled kernels support. */
+#define SFSEG_MAX_RS 8
+#define SFSEG_MAX_RT 4
+
+typedef struct sfseg_ctx sfseg_ctx; /* opaque; owned by the library */
+
+typedef enum {
+    SFSEG_OK = 0,
+    SFSEG_ERR_INVALID_ARG = -1, /* bad pointer, shape, radius, sigma, alpha, p, dtype */
+    SFSEG_ERR_OOM = -2,         /* device or pinned host allocation failed */
+    SFSEG_ERR_HIP = -3,         /* a HIP runtime call failed */
+    SFSEG_ERR_ZERO_NORM = -4,   /* start vector or an iterate has zero L2 norm */
+    SFSEG_ERR_NONFINITE = -5,   /* NaN/Inf in the inputs or the iteration, or S < 0 with p > 0 */
+    SFSEG_ERR_STATE = -6,       /* call out of order (e.g. eigvec before iterate) */
+    SFSEG_ERR_UNSUPPORTED = -7  /* radius beyond SFSEG_MAX_RS / SFSEG_MAX_RT */
+} sfseg_status;
+
+typedef enum {
+    SFSEG_F32 = 0,  /* float32 storage of w, F and the iterate */
+    SFSEG_BF16 = 1, /* bfloat16 storage, float32 filtering, float64 reductions */
+    SFSEG_F16 = 2   /* float16 storage, float32 filtering, float64 reductions */
+} sfseg_dtype;
+
+/* Graph and volume parameters (Sec. 3; the paper's experiments use alpha = 1
+ * and p = 0.1 or 0.2, Sec. 5).  Constraints: T, H, W >= 1 and
+ * T * H * W < 2^31; 0 <= r_t <= SFSEG_MAX_RT; 0 <= r_s <= SFSEG_MAX_RS;
+ * sigma_t, sigma_s > 0; alpha >= 0; p >= 0; storage a valid sfseg_dtype. */
+typedef struct {
+    int32_t T, H, W;
+    int32_t r_t, r_s;
+    int32_t storage; /* sfseg_dtype */
+    double sigma_t, sigma_s;
+    double alpha, p;
+} sfseg_config;
+
+/* Outcome of sfseg_power_iterate. */
+typedef struct {
+    int32_t iters;     /* steps taken (Eq. (4) + Eq. (8) each) */
+    int32_t converged; /* 1 if delta < tol was reached */
+    double delta;      /* ||x_k - x_{k-1}||_2 of the last step (unit iterates) */
+    double lambda;     /* x_{k-1}^T M x_{k-1}: Rayleigh quotient (Eq. (3)) of Eq. (2)'s M */
+} sfseg_result;
+
+/* GPU-event timings of the last sfseg_power_iterate call on the context's
+ * stream.  loop_ms covers only the fused step kernels (one launch per step),
+ * so loop_ms / iters is the average step-kernel duration plus launch gaps. */
+typedef struct {
+    double total_ms; /* whole call: start-vector copy/norm, steps, read-backs */
+    double init_ms;  /* start-vector copy and norm */
+    double loop_ms;  /* all step launches */
+    int32_t iters;
+    int32_t launches; /* step kernels launched (>= iters: launches after convergence exit at once) */
+} sfseg_timing;
+
+/* Fill *cfg with defaults: r_t = 1, r_s = 2, sigma_t = sigma_s = 1, alpha = 1,
+ * p = 0.2, storage SFSEG_F32; T, H, W are set to 0 and must be filled in.
+ * Host only. */
+void sfseg_config_default(sfseg_config *cfg);
+
+/* Check a configuration without touching the GPU.  Host only. */
+int sfseg_config_validate(const sfseg_config *cfg);
+
+/* Create a context for one clip (Sec. 3: "feature maps in, segmentation
+ * out").  Allocates the device buffers, then on `stream` computes w = S^p and
+ * copies F (F == NULL means F = S) and S (the default start vector, Alg. 1
+ * initialises X with S) into storage precision.  `stream` is a hipStream_t
+ * (NULL = the null stream).  The caller may release S and F once the stream
+ * has passed this point; the call itself waits for the input check to finish
+ * and returns SFSEG_ERR_NONFINITE if S or F holds NaN/Inf or S < 0 with
+ * p > 0.  On success *out owns the context; on failure *out is NULL. */
+int sfseg_create(const sfseg_config *cfg, const float *S, const float *F, void *stream,
+                 sfseg_ctx **out);
+
+/* Replace the features of an existing context (same shape and config) without
+ * reallocating: the prep of sfseg_create, ordered on the context's stream.
+ * Blocks until the input check finishes; invalidates the previous iterate. */
+int sfseg_set_features(sfseg_ctx *ctx, const float *S, const float *F);
+
+/* Power iteration (Eqs. (4), (8)): x <- x0 / ||x0|| (x0 == NULL means x0 = S,
+ * as in Alg. 1), then up to max_iters steps x <- M x / ||M x||, stopping after
+ * the first step whose change delta = ||x_k - x_{k-1}||_2 is below tol
+ * (tol <= 0 runs exactly max_iters steps).  x0 is a device float32 volume,
+ * read before the call returns.  Blocks the host once per chunk of steps and
+ * on return.  max_iters >= 0; max_iters == 0 only normalises x0.  Errors:
+ * SFSEG_ERR_ZERO_NORM if x0 or an iterate is zero, SFSEG_ERR_NONFINITE if an
+ * iterate overflows.  *res (host) may be NULL. */
+int sfseg_power_iterate(sfseg_ctx *ctx, const float *x0, int32_t max_iters, double tol,
+                        sfseg_result *res);
+
+/* Write the current unit-norm iterate x_k (float32, T*H*W, device memory
+ * owned by the caller) -- the soft segmentation of Eq. (8).  Ordered on the
+ * stream; does not block.  SFSEG_ERR_STATE before a successful
+ * sfseg_power_iterate. */
+int sfseg_eigvec(sfseg_ctx *ctx, float *out);
+
+/* One application of the operator, y = M x (Eq. (2) matrix, applied as the
+ * filtering form of Eq. (7)), without normalisation.  x and y are device
+ * float32 volumes (they may not alias); x is rounded to storage precision
+ * first.  Does not disturb the iteration state.  Blocks until done. */
+int sfseg_apply(sfseg_ctx *ctx, const float *x, float *y);
+
+/* Timings of the last sfseg_power_iterate (see sfseg_timing).  Host only. */
+int sfseg_last_timing(const sfseg_ctx *ctx, sfseg_timing *out);
+
+/* Release a context and its device buffers.  NULL-safe.  Waits for the
+ * context's stream first. */
+void sfseg_destroy(sfseg_ctx *ctx);
+
+/* Static description of a status code. */
+const char *sfseg_status_string(int status);
+
+/* Message of the last error raised on the calling thread ("" if none). */
+const char *sfseg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SFSEG_H */

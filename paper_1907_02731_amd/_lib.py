@@ -1,0 +1,118 @@
+"""ctypes binding of ``libsfseg.so`` (declared in include/sfseg.h).
+
+Argument marshalling only: every step of the power iteration runs in the
+library's gfx950 kernels.  PyTorch supplies device memory and streams.  The
+binding fails loudly when the library is missing -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsfseg.so")
+
+SFSEG_OK = 0
+SFSEG_ERR_INVALID_ARG = -1
+SFSEG_ERR_OOM = -2
+SFSEG_ERR_HIP = -3
+SFSEG_ERR_ZERO_NORM = -4
+SFSEG_ERR_NONFINITE = -5
+SFSEG_ERR_STATE = -6
+SFSEG_ERR_UNSUPPORTED = -7
+
+SFSEG_F32, SFSEG_BF16, SFSEG_F16 = 0, 1, 2
+DTYPES = {"f32": SFSEG_F32, "bf16": SFSEG_BF16, "f16": SFSEG_F16}
+MAX_RS, MAX_RT = 8, 4
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("T", ctypes.c_int32), ("H", ctypes.c_int32), ("W", ctypes.c_int32),
+                ("r_t", ctypes.c_int32), ("r_s", ctypes.c_int32), ("storage", ctypes.c_int32),
+                ("sigma_t", ctypes.c_double), ("sigma_s", ctypes.c_double),
+                ("alpha", ctypes.c_double), ("p", ctypes.c_double)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("delta", ctypes.c_double), ("lam", ctypes.c_double)]
+
+
+class Timing(ctypes.Structure):
+    _fields_ = [("total_ms", ctypes.c_double), ("init_ms", ctypes.c_double),
+                ("loop_ms", ctypes.c_double), ("iters", ctypes.c_int32),
+                ("launches", ctypes.c_int32)]
+
+
+class SfsegError(RuntimeError):
+    """A libsfseg entry point returned a negative status."""
+
+    def __init__(self, status: int, fn: str, msg: str):
+        super().__init__(f"{fn}: {msg} (status {status})")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load libsfseg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_1907_02731_amd.build` (hipcc, gfx950)")
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    pcfg = ctypes.POINTER(Config)
+    L.sfseg_config_default.argtypes = [pcfg]
+    L.sfseg_config_default.restype = None
+    L.sfseg_config_validate.argtypes = [pcfg]
+    L.sfseg_config_validate.restype = ctypes.c_int
+    L.sfseg_create.argtypes = [pcfg, P, P, P, ctypes.POINTER(P)]
+    L.sfseg_create.restype = ctypes.c_int
+    L.sfseg_set_features.argtypes = [P, P, P]
+    L.sfseg_set_features.restype = ctypes.c_int
+    L.sfseg_power_iterate.argtypes = [P, P, ctypes.c_int32, ctypes.c_double,
+                                      ctypes.POINTER(Result)]
+    L.sfseg_power_iterate.restype = ctypes.c_int
+    L.sfseg_eigvec.argtypes = [P, P]
+    L.sfseg_eigvec.restype = ctypes.c_int
+    L.sfseg_apply.argtypes = [P, P, P]
+    L.sfseg_apply.restype = ctypes.c_int
+    L.sfseg_last_timing.argtypes = [P, ctypes.POINTER(Timing)]
+    L.sfseg_last_timing.restype = ctypes.c_int
+    L.sfseg_destroy.argtypes = [P]
+    L.sfseg_destroy.restype = None
+    L.sfseg_status_string.argtypes = [ctypes.c_int]
+    L.sfseg_status_string.restype = ctypes.c_char_p
+    L.sfseg_last_error.argtypes = []
+    L.sfseg_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def check(status: int, fn: str) -> None:
+    if status != SFSEG_OK:
+        raise SfsegError(status, fn, lib().sfseg_last_error().decode(errors="replace"))
+
+
+def make_config(T: int, H: int, W: int, *, r_t: int = 1, r_s: int = 2,
+                sigma_t: float = 1.0, sigma_s: float = 1.0, alpha: float = 1.0,
+                p: float = 0.2, storage: str = "f32") -> Config:
+    if storage not in DTYPES:
+        raise ValueError(f"storage must be one of {sorted(DTYPES)}")
+    c = Config()
+    lib().sfseg_config_default(ctypes.byref(c))
+    c.T, c.H, c.W = int(T), int(H), int(W)
+    c.r_t, c.r_s = int(r_t), int(r_s)
+    c.sigma_t, c.sigma_s = float(sigma_t), float(sigma_s)
+    c.alpha, c.p = float(alpha), float(p)
+    c.storage = DTYPES[storage]
+    return c
+
+
+def validate(cfg: Config) -> int:
+    return int(lib().sfseg_config_validate(ctypes.byref(cfg)))

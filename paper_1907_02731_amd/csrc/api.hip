@@ -1,0 +1,435 @@
+// C ABI of the SFSeg power-iteration library (declared in include/sfseg.h).
+//
+// Host side: argument checks, buffer ownership, launch geometry and the
+// iteration loop.  Steps are launched in chunks on the context's stream; each
+// chunk is captured once as a HIP graph and replayed.  After each chunk the
+// host reads the 80-byte device state once to see whether the iteration has
+// stopped (later launches in a chunk exit at once when it has).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+
+#include "sfseg.h"
+#include "sfseg_internal.h"
+
+using sfseg::DevState;
+using sfseg::StepParams;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                 \
+    do {                                                                              \
+        hipError_t e_ = (expr);                                                       \
+        if (e_ != hipSuccess)                                                         \
+            return fail(e_ == hipErrorOutOfMemory ? SFSEG_ERR_OOM : SFSEG_ERR_HIP,    \
+                        "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__,     \
+                        __LINE__);                                                    \
+    } while (0)
+
+size_t dtype_size(int dt) { return dt == SFSEG_F32 ? 4 : 2; }
+
+constexpr int kChunk = 16;  // steps per captured graph / per host check
+
+}  // namespace
+
+struct sfseg_ctx {
+    sfseg_config cfg{};
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int64_t n = 0;
+    void* w = nullptr;   // S^p
+    void* f = nullptr;   // F
+    void* s0 = nullptr;  // S (default start vector)
+    void* buf[2] = {nullptr, nullptr};
+    void* apply_in = nullptr;
+    void* apply_out = nullptr;
+    DevState* st = nullptr;        // iteration state
+    DevState* st_apply = nullptr;  // state used by sfseg_apply
+    DevState* h_st = nullptr;      // pinned host copies: [0] final, [1..2] per-chunk
+    int32_t* d_bad = nullptr;
+    int32_t* h_bad = nullptr;
+    double* partials = nullptr;
+    int step_grid = 0;
+    int ew_grid = 0;  // grid of the element-wise kernels
+    int partial_slots = 0;
+    StepParams params[2]{};  // step from buf[0] -> buf[1] and from buf[1] -> buf[0]
+    hipGraphExec_t graph = nullptr;  // kChunk steps starting from buf[0]
+    hipEvent_t ev[5]{};
+    bool have_iterate = false;
+    int cur = 0;  // buffer holding the current iterate
+    sfseg_timing timing{};
+};
+
+extern "C" {
+
+void sfseg_config_default(sfseg_config* cfg) {
+    if (!cfg) return;
+    memset(cfg, 0, sizeof(*cfg));
+    cfg->r_t = 1;
+    cfg->r_s = 2;
+    cfg->storage = SFSEG_F32;
+    cfg->sigma_t = 1.0;
+    cfg->sigma_s = 1.0;
+    cfg->alpha = 1.0;
+    cfg->p = 0.2;
+}
+
+int sfseg_config_validate(const sfseg_config* c) {
+    if (!c) return fail(SFSEG_ERR_INVALID_ARG, "config is NULL");
+    if (c->T < 1 || c->H < 1 || c->W < 1)
+        return fail(SFSEG_ERR_INVALID_ARG, "T, H, W must be >= 1 (got %d, %d, %d)", c->T, c->H,
+                    c->W);
+    if ((int64_t)c->T * c->H * c->W >= ((int64_t)1 << 31))
+        return fail(SFSEG_ERR_INVALID_ARG, "T*H*W must be < 2^31");
+    if (c->r_t < 0 || c->r_s < 0)
+        return fail(SFSEG_ERR_INVALID_ARG, "radii must be >= 0 (r_t=%d, r_s=%d)", c->r_t, c->r_s);
+    if (c->r_t > SFSEG_MAX_RT || c->r_s > SFSEG_MAX_RS)
+        return fail(SFSEG_ERR_UNSUPPORTED, "radius beyond the compiled maximum (r_t<=%d, r_s<=%d)",
+                    SFSEG_MAX_RT, SFSEG_MAX_RS);
+    if (!(c->sigma_t > 0.0) || !(c->sigma_s > 0.0) || !isfinite(c->sigma_t) ||
+        !isfinite(c->sigma_s))
+        return fail(SFSEG_ERR_INVALID_ARG, "sigma_t and sigma_s must be finite and > 0");
+    if (!(c->alpha >= 0.0) || !isfinite(c->alpha))
+        return fail(SFSEG_ERR_INVALID_ARG, "alpha must be finite and >= 0");
+    if (!(c->p >= 0.0) || !isfinite(c->p))
+        return fail(SFSEG_ERR_INVALID_ARG, "p must be finite and >= 0");
+    if (c->storage != SFSEG_F32 && c->storage != SFSEG_BF16 && c->storage != SFSEG_F16)
+        return fail(SFSEG_ERR_INVALID_ARG, "storage must be SFSEG_F32, SFSEG_BF16 or SFSEG_F16");
+    return SFSEG_OK;
+}
+
+const char* sfseg_status_string(int s) {
+    switch (s) {
+        case SFSEG_OK: return "ok";
+        case SFSEG_ERR_INVALID_ARG: return "invalid argument";
+        case SFSEG_ERR_OOM: return "out of memory";
+        case SFSEG_ERR_HIP: return "HIP runtime error";
+        case SFSEG_ERR_ZERO_NORM: return "zero norm";
+        case SFSEG_ERR_NONFINITE: return "non-finite value";
+        case SFSEG_ERR_STATE: return "call out of order";
+        case SFSEG_ERR_UNSUPPORTED: return "unsupported configuration";
+        default: return "unknown status";
+    }
+}
+
+const char* sfseg_last_error(void) { return g_err; }
+
+void sfseg_destroy(sfseg_ctx* ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->graph) (void)hipGraphExecDestroy(ctx->graph);
+    for (auto& e : ctx->ev)
+        if (e) (void)hipEventDestroy(e);
+    void* dev[] = {ctx->w, ctx->f, ctx->s0, ctx->buf[0], ctx->buf[1], ctx->apply_in,
+                   ctx->apply_out, ctx->st, ctx->st_apply, ctx->d_bad, ctx->partials};
+    for (void* p : dev)
+        if (p) (void)hipFree(p);
+    if (ctx->h_st) (void)hipHostFree(ctx->h_st);
+    if (ctx->h_bad) (void)hipHostFree(ctx->h_bad);
+    delete ctx;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Gaussian taps of Eq. (1), one axis: exp(-d^2 / (2 sigma^2)), d = 0..r,
+// evaluated in float64 and rounded once to float32.
+void axis_taps(int r, double sigma, float* out) {
+    for (int d = 0; d <= r; ++d) out[d] = (float)exp(-(double)d * d / (2.0 * sigma * sigma));
+}
+
+int run_prep(sfseg_ctx* ctx, const float* S, const float* F) {
+    HIP_TRY(hipMemsetAsync(ctx->d_bad, 0, sizeof(int32_t), ctx->stream));
+    HIP_TRY(sfseg::launch_prep(ctx->cfg.storage, S, F, ctx->cfg.p, ctx->w, ctx->f, ctx->s0, ctx->n,
+                               ctx->d_bad, ctx->ew_grid, ctx->stream));
+    HIP_TRY(hipMemcpyAsync(ctx->h_bad, ctx->d_bad, sizeof(int32_t), hipMemcpyDeviceToHost,
+                           ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    ctx->have_iterate = false;
+    if (*ctx->h_bad)
+        return fail(SFSEG_ERR_NONFINITE, "S or F holds NaN/Inf, or S < 0 with p > 0");
+    return SFSEG_OK;
+}
+
+int setup(sfseg_ctx* ctx, const float* S, const float* F) {
+    const sfseg_config& c = ctx->cfg;
+    const int64_t n = ctx->n;
+    const size_t bytes = (size_t)n * dtype_size(c.storage);
+    HIP_TRY(hipGetDevice(&ctx->device));
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, ctx->device));
+    const int cus = prop.multiProcessorCount;
+
+    int occ = 1;
+    HIP_TRY(sfseg::step_max_blocks_per_cu(c.storage, c.r_s, c.r_t, &occ));
+    if (occ < 1) occ = 1;
+    const int tiles_x = (c.W + sfseg::TILE_X - 1) / sfseg::TILE_X;
+    const int tiles_y = (c.H + sfseg::TILE_Y - 1) / sfseg::TILE_Y;
+    const int64_t units = (int64_t)tiles_x * tiles_y * c.T;
+    // One resident wave of blocks, each with at least ~8 (tile, frame) units;
+    // a multiple of 8 so that every XCD gets the same number of blocks.
+    int64_t g = (int64_t)cus * occ;
+    const int64_t gmax = units / 8;
+    if (g > gmax) g = gmax;
+    g = (g / 8) * 8;
+    if (g < 8) g = 8;
+    ctx->step_grid = (int)g;
+    ctx->ew_grid = cus * 8;
+    ctx->partial_slots = ctx->step_grid > ctx->ew_grid ? ctx->step_grid : ctx->ew_grid;
+
+    HIP_TRY(hipMalloc(&ctx->w, bytes));
+    HIP_TRY(hipMalloc(&ctx->f, bytes));
+    HIP_TRY(hipMalloc(&ctx->s0, bytes));
+    HIP_TRY(hipMalloc(&ctx->buf[0], bytes));
+    HIP_TRY(hipMalloc(&ctx->buf[1], bytes));
+    HIP_TRY(hipMalloc((void**)&ctx->st, sizeof(DevState)));
+    HIP_TRY(hipMalloc((void**)&ctx->st_apply, sizeof(DevState)));
+    HIP_TRY(hipMalloc((void**)&ctx->d_bad, sizeof(int32_t)));
+    HIP_TRY(hipMalloc((void**)&ctx->partials, sizeof(double) * 2 * ctx->partial_slots));
+    HIP_TRY(hipHostMalloc((void**)&ctx->h_st, 3 * sizeof(DevState), hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc((void**)&ctx->h_bad, sizeof(int32_t), hipHostMallocDefault));
+    for (auto& e : ctx->ev) HIP_TRY(hipEventCreate(&e));
+    HIP_TRY(hipMemsetAsync(ctx->st, 0, sizeof(DevState), ctx->stream));
+    HIP_TRY(hipMemsetAsync(ctx->st_apply, 0, sizeof(DevState), ctx->stream));
+
+    for (int b = 0; b < 2; ++b) {
+        StepParams& p = ctx->params[b];
+        memset(&p, 0, sizeof(p));
+        p.x = ctx->buf[b];
+        p.y = ctx->buf[1 - b];
+        p.w = ctx->w;
+        p.f = ctx->f;
+        p.st = ctx->st;
+        p.partials = ctx->partials;
+        p.T = c.T;
+        p.H = c.H;
+        p.W = c.W;
+        p.tiles_x = tiles_x;
+        p.tiles_y = tiles_y;
+        p.n_units = units;
+        axis_taps(c.r_s, c.sigma_s, p.gs);
+        axis_taps(c.r_t, c.sigma_t, p.gt);
+        p.alpha = (float)c.alpha;
+    }
+    return run_prep(ctx, S, F);
+}
+
+// Gain that keeps the stored iterate values O(1): sqrt(N) / sum of all taps.
+// For w <= 1 and |1 - alpha dF^2| <= 1, sum(G) bounds lambda, so stored
+// values stay below sqrt(N) * max|x_i| <= sqrt(N).
+double storage_gain(const sfseg_config& c, int64_t n) {
+    double st = 0.0, ss = 0.0;
+    for (int d = -c.r_t; d <= c.r_t; ++d) st += exp(-(double)d * d / (2.0 * c.sigma_t * c.sigma_t));
+    for (int d = -c.r_s; d <= c.r_s; ++d) ss += exp(-(double)d * d / (2.0 * c.sigma_s * c.sigma_s));
+    return sqrt((double)n) / (st * ss * ss);
+}
+
+int launch_steps(sfseg_ctx* ctx, int first_buf, int count) {
+    for (int i = 0; i < count; ++i) {
+        const int b = (first_buf + i) & 1;
+        HIP_TRY(sfseg::launch_step(ctx->cfg.storage, ctx->cfg.r_s, ctx->cfg.r_t, ctx->params[b],
+                                   ctx->step_grid, ctx->stream));
+    }
+    return SFSEG_OK;
+}
+
+int ensure_graph(sfseg_ctx* ctx) {
+    if (ctx->graph) return SFSEG_OK;
+    hipGraph_t g = nullptr;
+    HIP_TRY(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+    int rc = launch_steps(ctx, 0, kChunk);
+    hipError_t e = hipStreamEndCapture(ctx->stream, &g);
+    if (rc != SFSEG_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(SFSEG_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&ctx->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        ctx->graph = nullptr;
+        return fail(SFSEG_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+    return SFSEG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sfseg_create(const sfseg_config* cfg, const float* S, const float* F, void* stream,
+                 sfseg_ctx** out) {
+    if (!out) return fail(SFSEG_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    int rc = sfseg_config_validate(cfg);
+    if (rc != SFSEG_OK) return rc;
+    if (!S) return fail(SFSEG_ERR_INVALID_ARG, "S is NULL");
+    sfseg_ctx* ctx = new (std::nothrow) sfseg_ctx();
+    if (!ctx) return fail(SFSEG_ERR_OOM, "host allocation failed");
+    ctx->cfg = *cfg;
+    ctx->stream = (hipStream_t)stream;
+    ctx->n = (int64_t)cfg->T * cfg->H * cfg->W;
+    rc = setup(ctx, S, F);
+    if (rc != SFSEG_OK) {
+        char keep[sizeof(g_err)];
+        memcpy(keep, g_err, sizeof(keep));
+        sfseg_destroy(ctx);
+        memcpy(g_err, keep, sizeof(keep));
+        return rc;
+    }
+    *out = ctx;
+    return SFSEG_OK;
+}
+
+int sfseg_set_features(sfseg_ctx* ctx, const float* S, const float* F) {
+    if (!ctx) return fail(SFSEG_ERR_INVALID_ARG, "ctx is NULL");
+    if (!S) return fail(SFSEG_ERR_INVALID_ARG, "S is NULL");
+    HIP_TRY(hipSetDevice(ctx->device));
+    return run_prep(ctx, S, F);
+}
+
+int sfseg_power_iterate(sfseg_ctx* ctx, const float* x0, int32_t max_iters, double tol,
+                        sfseg_result* res) {
+    if (!ctx) return fail(SFSEG_ERR_INVALID_ARG, "ctx is NULL");
+    if (max_iters < 0) return fail(SFSEG_ERR_INVALID_ARG, "max_iters must be >= 0");
+    if (isnan(tol)) return fail(SFSEG_ERR_INVALID_ARG, "tol is NaN");
+    HIP_TRY(hipSetDevice(ctx->device));
+    ctx->have_iterate = false;
+
+    // State set-up: tolerance, step budget and storage gain; init_kernel fills the rest.
+    DevState h{};
+    h.tol = tol;
+    h.max_iters = max_iters;
+    h.gain = storage_gain(ctx->cfg, ctx->n);
+    h.delta = INFINITY;
+    *ctx->h_st = h;
+    HIP_TRY(hipEventRecord(ctx->ev[0], ctx->stream));
+    HIP_TRY(hipMemcpyAsync(ctx->st, ctx->h_st, sizeof(DevState), hipMemcpyHostToDevice,
+                           ctx->stream));
+    HIP_TRY(sfseg::launch_init(ctx->cfg.storage, x0 ? (const void*)x0 : ctx->s0, x0 ? 0 : 1,
+                               ctx->buf[0], ctx->n, ctx->st, ctx->partials, ctx->ew_grid,
+                               ctx->stream));
+    HIP_TRY(hipEventRecord(ctx->ev[1], ctx->stream));
+
+    // Keep up to two chunks in flight: while chunk i runs, chunk i+1 is queued
+    // and the host inspects the state copied out after chunk i-1.
+    int launched = 0, enq = 0, chk = 0;
+    const bool use_graph = ctx->stream != nullptr && ensure_graph(ctx) == SFSEG_OK;
+    while (true) {
+        while (enq - chk < 2 && launched < max_iters) {
+            const int remaining = max_iters - launched;
+            if (use_graph && remaining >= kChunk && (launched & 1) == 0) {
+                HIP_TRY(hipGraphLaunch(ctx->graph, ctx->stream));
+                launched += kChunk;
+            } else {
+                const int cnt = remaining < kChunk ? remaining : kChunk;
+                int rc = launch_steps(ctx, launched & 1, cnt);
+                if (rc != SFSEG_OK) return rc;
+                launched += cnt;
+            }
+            HIP_TRY(hipMemcpyAsync(ctx->h_st + 1 + (enq & 1), ctx->st, sizeof(DevState),
+                                   hipMemcpyDeviceToHost, ctx->stream));
+            HIP_TRY(hipEventRecord(ctx->ev[3 + (enq & 1)], ctx->stream));
+            ++enq;
+        }
+        if (chk == enq) break;
+        HIP_TRY(hipEventSynchronize(ctx->ev[3 + (chk & 1)]));
+        const bool done = ctx->h_st[1 + (chk & 1)].done != 0;
+        ++chk;
+        if (done) break;
+    }
+    HIP_TRY(hipEventRecord(ctx->ev[2], ctx->stream));
+    HIP_TRY(hipMemcpyAsync(ctx->h_st, ctx->st, sizeof(DevState), hipMemcpyDeviceToHost,
+                           ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    const DevState& s = *ctx->h_st;
+
+    float t_init = 0.f, t_all = 0.f;
+    HIP_TRY(hipEventElapsedTime(&t_init, ctx->ev[0], ctx->ev[1]));
+    HIP_TRY(hipEventElapsedTime(&t_all, ctx->ev[0], ctx->ev[2]));
+    ctx->timing.total_ms = t_all;
+    ctx->timing.init_ms = t_init;
+    ctx->timing.loop_ms = t_all - t_init;
+    ctx->timing.iters = s.k;
+    ctx->timing.launches = launched;
+
+    if (res) {
+        res->iters = s.k;
+        res->converged = s.converged;
+        res->delta = s.delta;
+        res->lambda = s.lambda;
+    }
+    if (s.status != SFSEG_OK) {
+        return fail(s.status, s.status == SFSEG_ERR_ZERO_NORM
+                                  ? "zero norm (start vector or iterate %d)"
+                                  : "non-finite value (start vector or iterate %d)",
+                    s.k);
+    }
+    ctx->cur = s.k & 1;
+    ctx->have_iterate = true;
+    return SFSEG_OK;
+}
+
+int sfseg_eigvec(sfseg_ctx* ctx, float* out) {
+    if (!ctx || !out) return fail(SFSEG_ERR_INVALID_ARG, "ctx or out is NULL");
+    if (!ctx->have_iterate) return fail(SFSEG_ERR_STATE, "no iterate: call sfseg_power_iterate first");
+    HIP_TRY(hipSetDevice(ctx->device));
+    HIP_TRY(sfseg::launch_eigvec(ctx->cfg.storage, ctx->buf[ctx->cur], ctx->st, out, ctx->n,
+                                 ctx->ew_grid, ctx->stream));
+    return SFSEG_OK;
+}
+
+int sfseg_apply(sfseg_ctx* ctx, const float* x, float* y) {
+    if (!ctx || !x || !y) return fail(SFSEG_ERR_INVALID_ARG, "ctx, x or y is NULL");
+    if (x == (const float*)y) return fail(SFSEG_ERR_INVALID_ARG, "x and y may not alias");
+    HIP_TRY(hipSetDevice(ctx->device));
+    const size_t bytes = (size_t)ctx->n * dtype_size(ctx->cfg.storage);
+    if (!ctx->apply_in) HIP_TRY(hipMalloc(&ctx->apply_in, bytes));
+    if (!ctx->apply_out) HIP_TRY(hipMalloc(&ctx->apply_out, bytes));
+    DevState h{};
+    h.s = 1.0;
+    h.c = 1.0f;
+    h.gain = 1.0;
+    h.tol = -1.0;
+    h.max_iters = 1;
+    *ctx->h_st = h;
+    HIP_TRY(hipMemcpyAsync(ctx->st_apply, ctx->h_st, sizeof(DevState), hipMemcpyHostToDevice,
+                           ctx->stream));
+    HIP_TRY(sfseg::launch_to_storage(ctx->cfg.storage, x, ctx->apply_in, ctx->n, ctx->ew_grid,
+                                     ctx->stream));
+    StepParams p = ctx->params[0];
+    p.x = ctx->apply_in;
+    p.y = ctx->apply_out;
+    p.st = ctx->st_apply;
+    HIP_TRY(sfseg::launch_step(ctx->cfg.storage, ctx->cfg.r_s, ctx->cfg.r_t, p, ctx->step_grid,
+                               ctx->stream));
+    HIP_TRY(sfseg::launch_from_storage(ctx->cfg.storage, ctx->apply_out, y, ctx->n, ctx->ew_grid,
+                                       ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return SFSEG_OK;
+}
+
+int sfseg_last_timing(const sfseg_ctx* ctx, sfseg_timing* out) {
+    if (!ctx || !out) return fail(SFSEG_ERR_INVALID_ARG, "ctx or out is NULL");
+    *out = ctx->timing;
+    return SFSEG_OK;
+}
+
+}  // extern "C"

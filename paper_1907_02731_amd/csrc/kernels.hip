@@ -1,0 +1,198 @@
+// Element-wise gfx950 kernels of the SFSeg power iteration (prep, start
+// vector, eigenvector output, precision conversions) and the dispatch of the
+// fused step kernel (step_kernel.h) over storage precision and radii.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "step_kernel.h"
+
+namespace sfseg {
+
+hipError_t launch_step_f32(int rs, int rt, const StepParams& p, int grid, hipStream_t s);
+hipError_t launch_step_bf16(int rs, int rt, const StepParams& p, int grid, hipStream_t s);
+hipError_t launch_step_f16(int rs, int rt, const StepParams& p, int grid, hipStream_t s);
+hipError_t occ_step_f32(int rs, int rt, int* blocks);
+hipError_t occ_step_bf16(int rs, int rt, int* blocks);
+hipError_t occ_step_f16(int rs, int rt, int* blocks);
+
+namespace {
+using detail::Stor;
+using detail::block_partials_and_ticket;
+using detail::fixed_order_sum;
+
+// ---------------------------------------------------------------------------
+// Prep: w = S^p (0^p = 0 for p > 0, w = 1 for p = 0), F and a copy of S in
+// storage precision; flags NaN/Inf in S or F and S < 0 with p > 0.
+// ---------------------------------------------------------------------------
+template <typename TS>
+__global__ __launch_bounds__(256) void prep_kernel(const float* __restrict__ S,
+                                                   const float* __restrict__ F, float p,
+                                                   TS* __restrict__ w, TS* __restrict__ f,
+                                                   TS* __restrict__ s0, int64_t n,
+                                                   int32_t* bad) {
+    int badv = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const float sv = S[i];
+        const float fv = F ? F[i] : sv;
+        if (!isfinite(sv) || !isfinite(fv) || (p > 0.f && sv < 0.f)) badv = 1;
+        const float wv = (p == 0.f) ? 1.f : (sv > 0.f ? powf(sv, p) : 0.f);
+        Stor<TS>::st(w, i, wv);
+        Stor<TS>::st(f, i, fv);
+        Stor<TS>::st(s0, i, sv);
+    }
+    if (__any(badv) && (threadIdx.x & 63) == 0) atomicOr(bad, 1);
+}
+
+// Init: Y_0 = storage(x0); s = 1/||Y_0|| over the stored values; state reset.
+template <typename TS>
+__global__ __launch_bounds__(256) void init_kernel(const void* __restrict__ src, int src_is_storage,
+                                                   TS* __restrict__ y0, int64_t n, DevState* st,
+                                                   double* partials) {
+    __shared__ double fin[256];
+    double ss = 0.0, bad = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const float v = src_is_storage ? Stor<TS>::ld((const TS*)src, i) : ((const float*)src)[i];
+        const float q = Stor<TS>::rnd(v);
+        if (!isfinite(q)) bad = 1.0;
+        Stor<TS>::st(y0, i, q);
+        ss = fma((double)q, (double)q, ss);
+    }
+    if (block_partials_and_ticket<256>(ss, bad, partials, blockIdx.x, &st->ticket, gridDim.x)) {
+        const double tss = fixed_order_sum<256>(partials, gridDim.x, 0, fin);
+        const double tbad = fixed_order_sum<256>(partials, gridDim.x, 1, fin);
+        if (threadIdx.x == 0) {
+            const double nrm = sqrt(tss);
+            st->k = 0;
+            st->converged = 0;
+            st->lambda = 0.0;
+            st->delta = INFINITY;
+            st->status = SFSEG_OK;
+            st->done = (st->max_iters <= 0) ? 1 : 0;
+            if (tbad > 0.0 || !isfinite(nrm)) {
+                st->status = SFSEG_ERR_NONFINITE;
+                st->done = 1;
+            } else if (!(nrm > 0.0)) {
+                st->status = SFSEG_ERR_ZERO_NORM;
+                st->done = 1;
+            } else {
+                st->s = 1.0 / nrm;
+                st->c = (float)(st->s * st->gain);
+            }
+            __hip_atomic_store(&st->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+// out = s * Y_k (the unit iterate), float32.
+template <typename TS>
+__global__ __launch_bounds__(256) void eigvec_kernel(const TS* __restrict__ y, const DevState* st,
+                                                     float* __restrict__ out, int64_t n) {
+    const double s = st->s;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = (float)((double)Stor<TS>::ld(y, i) * s);
+}
+
+template <typename TS>
+__global__ __launch_bounds__(256) void to_storage_kernel(const float* __restrict__ src,
+                                                         TS* __restrict__ dst, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        Stor<TS>::st(dst, i, src[i]);
+}
+
+template <typename TS>
+__global__ __launch_bounds__(256) void from_storage_kernel(const TS* __restrict__ src,
+                                                           float* __restrict__ dst, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = Stor<TS>::ld(src, i);
+}
+
+}  // namespace
+
+hipError_t launch_step(int dtype, int rs, int rt, const StepParams& p, int grid, hipStream_t s) {
+    if (rs < 0 || rs > SFSEG_MAX_RS || rt < 0 || rt > SFSEG_MAX_RT) return hipErrorInvalidValue;
+    switch (dtype) {
+        case SFSEG_F32: return launch_step_f32(rs, rt, p, grid, s);
+        case SFSEG_BF16: return launch_step_bf16(rs, rt, p, grid, s);
+        case SFSEG_F16: return launch_step_f16(rs, rt, p, grid, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t step_max_blocks_per_cu(int dtype, int rs, int rt, int* blocks) {
+    if (rs < 0 || rs > SFSEG_MAX_RS || rt < 0 || rt > SFSEG_MAX_RT) return hipErrorInvalidValue;
+    switch (dtype) {
+        case SFSEG_F32: return occ_step_f32(rs, rt, blocks);
+        case SFSEG_BF16: return occ_step_bf16(rs, rt, blocks);
+        case SFSEG_F16: return occ_step_f16(rs, rt, blocks);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+#define SFSEG_DISPATCH_DTYPE(dtype, TS, ...)          \
+    switch (dtype) {                                  \
+        case SFSEG_F32: {                             \
+            using TS = float;                         \
+            __VA_ARGS__;                              \
+            break;                                    \
+        }                                             \
+        case SFSEG_BF16: {                            \
+            using TS = __bf16;                        \
+            __VA_ARGS__;                              \
+            break;                                    \
+        }                                             \
+        case SFSEG_F16: {                             \
+            using TS = _Float16;                      \
+            __VA_ARGS__;                              \
+            break;                                    \
+        }                                             \
+        default:                                      \
+            return hipErrorInvalidValue;              \
+    }
+
+hipError_t launch_prep(int dtype, const float* S, const float* F, double p, void* w, void* f,
+                       void* s0, int64_t n, int32_t* bad, int grid, hipStream_t stream) {
+    SFSEG_DISPATCH_DTYPE(dtype, TS,
+                         hipLaunchKernelGGL((prep_kernel<TS>), dim3(grid), dim3(256), 0, stream, S,
+                                            F, (float)p, (TS*)w, (TS*)f, (TS*)s0, n, bad));
+    return hipGetLastError();
+}
+
+hipError_t launch_init(int dtype, const void* src, int src_is_storage, void* y0, int64_t n,
+                       DevState* st, double* partials, int grid, hipStream_t stream) {
+    SFSEG_DISPATCH_DTYPE(dtype, TS,
+                         hipLaunchKernelGGL((init_kernel<TS>), dim3(grid), dim3(256), 0, stream,
+                                            src, src_is_storage, (TS*)y0, n, st, partials));
+    return hipGetLastError();
+}
+
+hipError_t launch_eigvec(int dtype, const void* y, const DevState* st, float* out, int64_t n,
+                         int grid, hipStream_t stream) {
+    SFSEG_DISPATCH_DTYPE(dtype, TS,
+                         hipLaunchKernelGGL((eigvec_kernel<TS>), dim3(grid), dim3(256), 0, stream,
+                                            (const TS*)y, st, out, n));
+    return hipGetLastError();
+}
+
+hipError_t launch_to_storage(int dtype, const float* src, void* dst, int64_t n, int grid,
+                             hipStream_t stream) {
+    SFSEG_DISPATCH_DTYPE(dtype, TS,
+                         hipLaunchKernelGGL((to_storage_kernel<TS>), dim3(grid), dim3(256), 0,
+                                            stream, src, (TS*)dst, n));
+    return hipGetLastError();
+}
+
+hipError_t launch_from_storage(int dtype, const void* src, float* dst, int64_t n, int grid,
+                               hipStream_t stream) {
+    SFSEG_DISPATCH_DTYPE(dtype, TS,
+                         hipLaunchKernelGGL((from_storage_kernel<TS>), dim3(grid), dim3(256), 0,
+                                            stream, (const TS*)src, dst, n));
+    return hipGetLastError();
+}
+
+}  // namespace sfseg

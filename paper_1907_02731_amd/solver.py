@@ -1,0 +1,143 @@
+"""PyTorch-facing wrapper of the libsfseg C ABI.
+
+``Solver`` owns one library context for one clip.  It runs on a stream of
+its own (default priority) and orders itself after / before the caller's
+current stream with stream waits, so tensors produced or consumed on the
+caller's stream need no extra synchronisation.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import Optional
+
+import torch
+
+from . import _lib
+
+
+@dataclass
+class IterResult:
+    iters: int
+    converged: bool
+    delta: float
+    lam: float
+
+
+def _dev_ptr(t: Optional[torch.Tensor], name: str, shape) -> Optional[int]:
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != torch.float32:
+        raise TypeError(f"{name} must be float32")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t.data_ptr()
+
+
+class Solver:
+    """Power iteration for the principal eigenvector of one clip's graph.
+
+    Parameters follow the graph definition (w = S^p, Gaussian box of radii
+    r_t / r_s and widths sigma_t / sigma_s, Taylor pairwise term with alpha).
+    ``S`` and ``F`` are float32 CUDA tensors of shape (T, H, W); F=None uses S.
+    """
+
+    def __init__(self, S: torch.Tensor, F: Optional[torch.Tensor] = None, *, r_t: int = 1,
+                 r_s: int = 2, sigma_t: float = 1.0, sigma_s: float = 1.0,
+                 alpha: float = 1.0, p: float = 0.2, storage: str = "f32",
+                 stream: Optional[torch.cuda.Stream] = None):
+        L = _lib.lib()
+        if S.dim() != 3:
+            raise ValueError("S must be (T, H, W)")
+        self.shape = tuple(int(v) for v in S.shape)
+        self.device = S.device
+        self.cfg = _lib.make_config(*self.shape, r_t=r_t, r_s=r_s, sigma_t=sigma_t,
+                                    sigma_s=sigma_s, alpha=alpha, p=p, storage=storage)
+        ps = _dev_ptr(S, "S", self.shape)
+        pf = _dev_ptr(F, "F", self.shape)
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=S.device)
+        self._ctx = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            self.stream.wait_stream(torch.cuda.current_stream())
+            _lib.check(L.sfseg_create(ctypes.byref(self.cfg), ps, pf,
+                                      ctypes.c_void_p(self.stream.cuda_stream),
+                                      ctypes.byref(self._ctx)), "sfseg_create")
+
+    # -- context management ------------------------------------------------
+    def close(self) -> None:
+        if getattr(self, "_ctx", None) is not None and self._ctx.value:
+            with torch.cuda.device(self.device):
+                _lib.lib().sfseg_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _handle(self):
+        if not self._ctx.value:
+            raise RuntimeError("solver is closed")
+        return self._ctx
+
+    # -- entry points --------------------------------------------------------
+    def set_features(self, S: torch.Tensor, F: Optional[torch.Tensor] = None) -> None:
+        ps = _dev_ptr(S, "S", self.shape)
+        pf = _dev_ptr(F, "F", self.shape)
+        with torch.cuda.device(self.device):
+            self.stream.wait_stream(torch.cuda.current_stream())
+            _lib.check(_lib.lib().sfseg_set_features(self._handle(), ps, pf),
+                       "sfseg_set_features")
+
+    def iterate(self, x0: Optional[torch.Tensor] = None, max_iters: int = 100,
+                tol: float = 1e-5) -> IterResult:
+        px = _dev_ptr(x0, "x0", self.shape)
+        res = _lib.Result()
+        with torch.cuda.device(self.device):
+            self.stream.wait_stream(torch.cuda.current_stream())
+            _lib.check(_lib.lib().sfseg_power_iterate(self._handle(), px, int(max_iters),
+                                                      float(tol), ctypes.byref(res)),
+                       "sfseg_power_iterate")
+        return IterResult(int(res.iters), bool(res.converged), float(res.delta), float(res.lam))
+
+    def eigvec(self, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        with torch.cuda.device(self.device):
+            if out is None:
+                with torch.cuda.stream(self.stream):
+                    out = torch.empty(self.shape, dtype=torch.float32, device=self.device)
+            else:
+                self.stream.wait_stream(torch.cuda.current_stream())
+            po = _dev_ptr(out, "out", self.shape)
+            _lib.check(_lib.lib().sfseg_eigvec(self._handle(), po), "sfseg_eigvec")
+            torch.cuda.current_stream().wait_stream(self.stream)
+        return out
+
+    def apply(self, x: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        px = _dev_ptr(x, "x", self.shape)
+        with torch.cuda.device(self.device):
+            if out is None:
+                with torch.cuda.stream(self.stream):
+                    out = torch.empty(self.shape, dtype=torch.float32, device=self.device)
+            po = _dev_ptr(out, "out", self.shape)
+            self.stream.wait_stream(torch.cuda.current_stream())
+            _lib.check(_lib.lib().sfseg_apply(self._handle(), px, po), "sfseg_apply")
+            torch.cuda.current_stream().wait_stream(self.stream)
+        return out
+
+    def timing(self) -> dict:
+        t = _lib.Timing()
+        _lib.check(_lib.lib().sfseg_last_timing(self._handle(), ctypes.byref(t)),
+                   "sfseg_last_timing")
+        return {"total_ms": t.total_ms, "init_ms": t.init_ms, "loop_ms": t.loop_ms,
+                "iters": int(t.iters), "launches": int(t.launches)}
