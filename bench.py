@@ -49,8 +49,10 @@ def parse():
     ap.add_argument("--max-iters", type=int, default=5000)
     ap.add_argument("--alpha", type=float, default=1.0)
     ap.add_argument("--p", type=float, default=0.2)
+    ap.add_argument("--iters", type=int, default=0,
+                    help="run exactly this many steps per solve (tol = 0); for profiling")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=3,
+    ap.add_argument("--cpu-steps", type=int, default=20,
                     help="oracle power-iteration steps timed for the CPU baseline")
     return ap.parse_args()
 
@@ -95,9 +97,11 @@ def main():
               storage=args.storage)
     sol = Solver(St, **kw)
 
+    max_iters, tol = (args.iters, 0.0) if args.iters > 0 else (args.max_iters, args.tol)
+
     def one_step():
         sol.set_features(St)
-        r = sol.iterate(max_iters=args.max_iters, tol=args.tol)
+        r = sol.iterate(max_iters=max_iters, tol=tol)
         sol.eigvec(out)
         return r, sol.timing()
 

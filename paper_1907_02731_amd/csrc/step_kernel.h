@@ -355,9 +355,9 @@ __global__ __launch_bounds__(NT) void step_kernel(StepParams p) {
 #pragma unroll
                             for (int m = 0; m < NR; ++m) {
                                 const int slot = (j + 1 + m) % NR;
-                                A = fmaf(gt[m], ring[slot][0][i], A);
-                                B = fmaf(gt[m], ring[slot][1][i], B);
-                                C = fmaf(gt[m], ring[slot][2][i], C);
+                                A = fmaf(gt[m], ring[slot][0][i], A);  // G * u
+                                C = fmaf(gt[m], ring[slot][1][i], C);  // G * (F u)
+                                B = fmaf(gt[m], ring[slot][2][i], B);  // G * (F^2 u)
                             }
                             const float xc = cring[jc][0][i];
                             const float wc = cring[jc][1][i];
