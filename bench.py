@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--p", type=float, default=0.2)
     ap.add_argument("--iters", type=int, default=0,
                     help="run exactly this many steps per solve (tol = 0); for profiling")
+    ap.add_argument("--shape", type=int, default=-1, help="step-kernel block shape (0/1)")
+    ap.add_argument("--chunks", type=int, default=0, help="frame runs per tile")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=20,
                     help="oracle power-iteration steps timed for the CPU baseline")
@@ -96,6 +98,10 @@ def main():
     kw = dict(r_t=r_t, r_s=r_s, sigma_t=s_t, sigma_s=s_s, alpha=args.alpha, p=args.p,
               storage=args.storage)
     sol = Solver(St, **kw)
+    if args.shape >= 0 or args.chunks > 0:
+        pl = sol.plan()
+        sol.set_plan(args.shape if args.shape >= 0 else pl["shape"],
+                     args.chunks if args.chunks > 0 else pl["chunks"])
 
     max_iters, tol = (args.iters, 0.0) if args.iters > 0 else (args.max_iters, args.tol)
 
@@ -143,6 +149,7 @@ def main():
             "T": T, "H": H, "W": W, "tol": args.tol,
         },
         "iters_per_step": iters,
+        "plan": sol.plan(),
         "converged": bool(last.converged),
         "delta": last.delta,
         "lambda": last.lam,

@@ -95,6 +95,18 @@ typedef struct {
     int32_t launches; /* step kernels launched (>= iters: launches after convergence exit at once) */
 } sfseg_timing;
 
+/* Work plan of the step kernel: block shape (0 = 256 threads with 4 outputs
+ * each along x, 1 = 512 threads with 2), number of equal runs of frames each
+ * tile's time axis is cut into, and the resulting grid.  Every plan applies
+ * the same per-voxel arithmetic; plans differ only in how the float64 partial
+ * sums of the norms are grouped. */
+typedef struct {
+    int32_t shape;
+    int32_t chunks;
+    int32_t blocks;  /* step-kernel grid (filled in by sfseg_get_plan) */
+    int32_t threads; /* threads per block (filled in by sfseg_get_plan) */
+} sfseg_plan;
+
 /* Fill *cfg with defaults: r_t = 1, r_s = 2, sigma_t = sigma_s = 1, alpha = 1,
  * p = 0.2, storage SFSEG_F32; T, H, W are set to 0 and must be filled in.
  * Host only. */
@@ -141,6 +153,15 @@ int sfseg_eigvec(sfseg_ctx *ctx, float *out);
  * float32 volumes (they may not alias); x is rounded to storage precision
  * first.  Does not disturb the iteration state.  Blocks until done. */
 int sfseg_apply(sfseg_ctx *ctx, const float *x, float *y);
+
+/* Current work plan of the step kernel.  Host only. */
+int sfseg_get_plan(const sfseg_ctx *ctx, sfseg_plan *out);
+
+/* Choose the work plan (see sfseg_plan): shape 0 or 1, 1 <= chunks <=
+ * max(1, T / (4 r_t + 4)).  Blocks until the new work list is on the device;
+ * SFSEG_ERR_INVALID_ARG for values out of range.  Does not disturb the
+ * iterate. */
+int sfseg_set_plan(sfseg_ctx *ctx, int32_t shape, int32_t chunks);
 
 /* Timings of the last sfseg_power_iterate (see sfseg_timing).  Host only. */
 int sfseg_last_timing(const sfseg_ctx *ctx, sfseg_timing *out);

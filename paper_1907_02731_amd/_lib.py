@@ -45,6 +45,11 @@ class Timing(ctypes.Structure):
                 ("launches", ctypes.c_int32)]
 
 
+class Plan(ctypes.Structure):
+    _fields_ = [("shape", ctypes.c_int32), ("chunks", ctypes.c_int32),
+                ("blocks", ctypes.c_int32), ("threads", ctypes.c_int32)]
+
+
 class SfsegError(RuntimeError):
     """A libsfseg entry point returned a negative status."""
 
@@ -82,6 +87,10 @@ def lib():
     L.sfseg_eigvec.restype = ctypes.c_int
     L.sfseg_apply.argtypes = [P, P, P]
     L.sfseg_apply.restype = ctypes.c_int
+    L.sfseg_get_plan.argtypes = [P, ctypes.POINTER(Plan)]
+    L.sfseg_get_plan.restype = ctypes.c_int
+    L.sfseg_set_plan.argtypes = [P, ctypes.c_int32, ctypes.c_int32]
+    L.sfseg_set_plan.restype = ctypes.c_int
     L.sfseg_last_timing.argtypes = [P, ctypes.POINTER(Timing)]
     L.sfseg_last_timing.restype = ctypes.c_int
     L.sfseg_destroy.argtypes = [P]

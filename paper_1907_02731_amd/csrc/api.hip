@@ -13,6 +13,7 @@
 #include <string.h>
 
 #include <new>
+#include <vector>
 
 #include "sfseg.h"
 #include "sfseg_internal.h"
@@ -64,6 +65,12 @@ struct sfseg_ctx {
     int32_t* d_bad = nullptr;
     int32_t* h_bad = nullptr;
     double* partials = nullptr;
+    int4* items = nullptr;  // step-kernel work items, one per block
+    size_t items_cap = 0;   // capacity of `items` in entries
+    sfseg::Layout L{};
+    int cus = 0;
+    int shape = 0;          // step-kernel block shape (sfseg::step_threads)
+    int chunks = 1;         // runs of frames per tile
     int step_grid = 0;
     int ew_grid = 0;  // grid of the element-wise kernels
     int partial_slots = 0;
@@ -137,7 +144,8 @@ void sfseg_destroy(sfseg_ctx* ctx) {
     for (auto& e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
     void* dev[] = {ctx->w, ctx->f, ctx->s0, ctx->buf[0], ctx->buf[1], ctx->apply_in,
-                   ctx->apply_out, ctx->st, ctx->st_apply, ctx->d_bad, ctx->partials};
+                   ctx->apply_out, ctx->st, ctx->st_apply, ctx->d_bad, ctx->partials,
+                   ctx->items};
     for (void* p : dev)
         if (p) (void)hipFree(p);
     if (ctx->h_st) (void)hipHostFree(ctx->h_st);
@@ -157,7 +165,7 @@ void axis_taps(int r, double sigma, float* out) {
 
 int run_prep(sfseg_ctx* ctx, const float* S, const float* F) {
     HIP_TRY(hipMemsetAsync(ctx->d_bad, 0, sizeof(int32_t), ctx->stream));
-    HIP_TRY(sfseg::launch_prep(ctx->cfg.storage, S, F, ctx->cfg.p, ctx->w, ctx->f, ctx->s0, ctx->n,
+    HIP_TRY(sfseg::launch_prep(ctx->cfg.storage, S, F, ctx->cfg.p, ctx->w, ctx->f, ctx->s0, ctx->L,
                                ctx->d_bad, ctx->ew_grid, ctx->stream));
     HIP_TRY(hipMemcpyAsync(ctx->h_bad, ctx->d_bad, sizeof(int32_t), hipMemcpyDeviceToHost,
                            ctx->stream));
@@ -168,31 +176,110 @@ int run_prep(sfseg_ctx* ctx, const float* S, const float* F) {
     return SFSEG_OK;
 }
 
+// Padded layout for the step kernel: the picture sits at row PT = r_s and
+// column PL = r_s rounded up to a multiple of 4 (16-byte aligned output rows);
+// the frame holds every tile plus its halo.
+sfseg::Layout make_layout(const sfseg_config& c) {
+    sfseg::Layout L{};
+    L.T = c.T;
+    L.H = c.H;
+    L.W = c.W;
+    L.tiles_x = (c.W + sfseg::TILE_X - 1) / sfseg::TILE_X;
+    L.tiles_y = (c.H + sfseg::TILE_Y - 1) / sfseg::TILE_Y;
+    L.PT = c.r_s;
+    L.PL = (c.r_s + 3) / 4 * 4;
+    L.Hp = L.PT + L.tiles_y * sfseg::TILE_Y + c.r_s;
+    L.Wp = (L.PL + L.tiles_x * sfseg::TILE_X + c.r_s + 3) / 4 * 4;
+    L.frame = (int64_t)L.Hp * L.Wp;
+    L.total = L.frame * L.T;
+    return L;
+}
+
+// Work items of the step kernel: every tile over `chunks` equal runs of
+// frames, chunk-major, then tile rows, then tile columns; padded with empty
+// items to a multiple of 8 blocks (one share per XCD).
+std::vector<int4> plan_items(const sfseg::Layout& L, int chunks) {
+    std::vector<int4> items;
+    for (int ch = 0; ch < chunks; ++ch) {
+        const int t0 = (int)((int64_t)L.T * ch / chunks), t1 = (int)((int64_t)L.T * (ch + 1) / chunks);
+        if (t1 <= t0) continue;
+        for (int ty = 0; ty < L.tiles_y; ++ty)
+            for (int tx = 0; tx < L.tiles_x; ++tx)
+                items.push_back(make_int4(tx * sfseg::TILE_X, ty * sfseg::TILE_Y, t0, t1));
+    }
+    while (items.size() % 8) items.push_back(make_int4(0, 0, 0, 0));
+    return items;
+}
+
+// Install a work plan: block shape and number of frame runs per tile.  The
+// work items and the grid follow from it; a captured graph is dropped.
+int install_plan(sfseg_ctx* ctx, int shape, int chunks) {
+    const std::vector<int4> items = plan_items(ctx->L, chunks);
+    if (items.size() > ctx->items_cap) {
+        if (ctx->items) HIP_TRY(hipFree(ctx->items));
+        ctx->items = nullptr;
+        HIP_TRY(hipMalloc((void**)&ctx->items, sizeof(int4) * items.size()));
+        ctx->items_cap = items.size();
+    }
+    const int grid = (int)items.size();
+    const int need = grid > ctx->ew_grid ? grid : ctx->ew_grid;
+    if (need > ctx->partial_slots) {
+        if (ctx->partials) HIP_TRY(hipFree(ctx->partials));
+        ctx->partials = nullptr;
+        HIP_TRY(hipMalloc((void**)&ctx->partials, sizeof(double) * 2 * need));
+        ctx->partial_slots = need;
+    }
+    HIP_TRY(hipMemcpyAsync(ctx->items, items.data(), sizeof(int4) * items.size(),
+                           hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    ctx->shape = shape;
+    ctx->chunks = chunks;
+    ctx->step_grid = grid;
+    for (auto& p : ctx->params) {
+        p.items = ctx->items;
+        p.partials = ctx->partials;
+    }
+    if (ctx->graph) {
+        (void)hipGraphExecDestroy(ctx->graph);
+        ctx->graph = nullptr;
+    }
+    return SFSEG_OK;
+}
+
+// Longest useful split of time: every run keeps at least 4 r_t + 4 frames
+// (the register ring warms up over 2 r_t of them).
+int max_chunks(const sfseg_config& c) {
+    const int m = c.T / (4 * c.r_t + 4);
+    return m > 1 ? m : 1;
+}
+
+// Default plan: the 256-thread shape; one run per tile when the tiles alone
+// fill the resident block slots, otherwise enough runs to fill them.
+int default_plan(sfseg_ctx* ctx, int* shape, int* chunks) {
+    const sfseg_config& c = ctx->cfg;
+    *shape = 0;
+    int occ = 1;
+    HIP_TRY(sfseg::step_max_blocks_per_cu(c.storage, *shape, c.r_s, c.r_t, &occ));
+    if (occ < 1) occ = 1;
+    const int tiles = ctx->L.tiles_x * ctx->L.tiles_y;
+    int ch = ctx->cus * occ / tiles;
+    if (ch > max_chunks(c)) ch = max_chunks(c);
+    *chunks = ch < 1 ? 1 : ch;
+    return SFSEG_OK;
+}
+
 int setup(sfseg_ctx* ctx, const float* S, const float* F) {
     const sfseg_config& c = ctx->cfg;
-    const int64_t n = ctx->n;
-    const size_t bytes = (size_t)n * dtype_size(c.storage);
+    ctx->L = make_layout(c);
+    const sfseg::Layout& L = ctx->L;
+    if (L.total * (int64_t)dtype_size(c.storage) >= ((int64_t)1 << 31))
+        return fail(SFSEG_ERR_INVALID_ARG, "padded volume exceeds 2 GiB per array");
+    const size_t bytes = (size_t)L.total * dtype_size(c.storage);
     HIP_TRY(hipGetDevice(&ctx->device));
     hipDeviceProp_t prop;
     HIP_TRY(hipGetDeviceProperties(&prop, ctx->device));
-    const int cus = prop.multiProcessorCount;
-
-    int occ = 1;
-    HIP_TRY(sfseg::step_max_blocks_per_cu(c.storage, c.r_s, c.r_t, &occ));
-    if (occ < 1) occ = 1;
-    const int tiles_x = (c.W + sfseg::TILE_X - 1) / sfseg::TILE_X;
-    const int tiles_y = (c.H + sfseg::TILE_Y - 1) / sfseg::TILE_Y;
-    const int64_t units = (int64_t)tiles_x * tiles_y * c.T;
-    // One resident wave of blocks, each with at least ~8 (tile, frame) units;
-    // a multiple of 8 so that every XCD gets the same number of blocks.
-    int64_t g = (int64_t)cus * occ;
-    const int64_t gmax = units / 8;
-    if (g > gmax) g = gmax;
-    g = (g / 8) * 8;
-    if (g < 8) g = 8;
-    ctx->step_grid = (int)g;
-    ctx->ew_grid = cus * 8;
-    ctx->partial_slots = ctx->step_grid > ctx->ew_grid ? ctx->step_grid : ctx->ew_grid;
+    ctx->cus = prop.multiProcessorCount;
+    ctx->ew_grid = ctx->cus * 8;
 
     HIP_TRY(hipMalloc(&ctx->w, bytes));
     HIP_TRY(hipMalloc(&ctx->f, bytes));
@@ -202,10 +289,12 @@ int setup(sfseg_ctx* ctx, const float* S, const float* F) {
     HIP_TRY(hipMalloc((void**)&ctx->st, sizeof(DevState)));
     HIP_TRY(hipMalloc((void**)&ctx->st_apply, sizeof(DevState)));
     HIP_TRY(hipMalloc((void**)&ctx->d_bad, sizeof(int32_t)));
-    HIP_TRY(hipMalloc((void**)&ctx->partials, sizeof(double) * 2 * ctx->partial_slots));
     HIP_TRY(hipHostMalloc((void**)&ctx->h_st, 3 * sizeof(DevState), hipHostMallocDefault));
     HIP_TRY(hipHostMalloc((void**)&ctx->h_bad, sizeof(int32_t), hipHostMallocDefault));
     for (auto& e : ctx->ev) HIP_TRY(hipEventCreate(&e));
+    // The padding of every volume must hold zeros; nothing ever writes it.
+    void* vols[] = {ctx->w, ctx->f, ctx->s0, ctx->buf[0], ctx->buf[1]};
+    for (void* v : vols) HIP_TRY(hipMemsetAsync(v, 0, bytes, ctx->stream));
     HIP_TRY(hipMemsetAsync(ctx->st, 0, sizeof(DevState), ctx->stream));
     HIP_TRY(hipMemsetAsync(ctx->st_apply, 0, sizeof(DevState), ctx->stream));
 
@@ -217,17 +306,20 @@ int setup(sfseg_ctx* ctx, const float* S, const float* F) {
         p.w = ctx->w;
         p.f = ctx->f;
         p.st = ctx->st;
-        p.partials = ctx->partials;
         p.T = c.T;
-        p.H = c.H;
-        p.W = c.W;
-        p.tiles_x = tiles_x;
-        p.tiles_y = tiles_y;
-        p.n_units = units;
+        p.Wp = L.Wp;
+        p.PT = L.PT;
+        p.PL = L.PL;
+        p.frame = L.frame;
         axis_taps(c.r_s, c.sigma_s, p.gs);
         axis_taps(c.r_t, c.sigma_t, p.gt);
         p.alpha = (float)c.alpha;
     }
+    int shape = 0, chunks = 1;
+    int rc = default_plan(ctx, &shape, &chunks);
+    if (rc != SFSEG_OK) return rc;
+    rc = install_plan(ctx, shape, chunks);
+    if (rc != SFSEG_OK) return rc;
     return run_prep(ctx, S, F);
 }
 
@@ -244,8 +336,8 @@ double storage_gain(const sfseg_config& c, int64_t n) {
 int launch_steps(sfseg_ctx* ctx, int first_buf, int count) {
     for (int i = 0; i < count; ++i) {
         const int b = (first_buf + i) & 1;
-        HIP_TRY(sfseg::launch_step(ctx->cfg.storage, ctx->cfg.r_s, ctx->cfg.r_t, ctx->params[b],
-                                   ctx->step_grid, ctx->stream));
+        HIP_TRY(sfseg::launch_step(ctx->cfg.storage, ctx->shape, ctx->cfg.r_s, ctx->cfg.r_t,
+                                   ctx->params[b], ctx->step_grid, ctx->stream));
     }
     return SFSEG_OK;
 }
@@ -324,7 +416,7 @@ int sfseg_power_iterate(sfseg_ctx* ctx, const float* x0, int32_t max_iters, doub
     HIP_TRY(hipMemcpyAsync(ctx->st, ctx->h_st, sizeof(DevState), hipMemcpyHostToDevice,
                            ctx->stream));
     HIP_TRY(sfseg::launch_init(ctx->cfg.storage, x0 ? (const void*)x0 : ctx->s0, x0 ? 0 : 1,
-                               ctx->buf[0], ctx->n, ctx->st, ctx->partials, ctx->ew_grid,
+                               ctx->buf[0], ctx->L, ctx->st, ctx->partials, ctx->ew_grid,
                                ctx->stream));
     HIP_TRY(hipEventRecord(ctx->ev[1], ctx->stream));
 
@@ -391,7 +483,7 @@ int sfseg_eigvec(sfseg_ctx* ctx, float* out) {
     if (!ctx || !out) return fail(SFSEG_ERR_INVALID_ARG, "ctx or out is NULL");
     if (!ctx->have_iterate) return fail(SFSEG_ERR_STATE, "no iterate: call sfseg_power_iterate first");
     HIP_TRY(hipSetDevice(ctx->device));
-    HIP_TRY(sfseg::launch_eigvec(ctx->cfg.storage, ctx->buf[ctx->cur], ctx->st, out, ctx->n,
+    HIP_TRY(sfseg::launch_eigvec(ctx->cfg.storage, ctx->buf[ctx->cur], ctx->st, out, ctx->L,
                                  ctx->ew_grid, ctx->stream));
     return SFSEG_OK;
 }
@@ -400,9 +492,15 @@ int sfseg_apply(sfseg_ctx* ctx, const float* x, float* y) {
     if (!ctx || !x || !y) return fail(SFSEG_ERR_INVALID_ARG, "ctx, x or y is NULL");
     if (x == (const float*)y) return fail(SFSEG_ERR_INVALID_ARG, "x and y may not alias");
     HIP_TRY(hipSetDevice(ctx->device));
-    const size_t bytes = (size_t)ctx->n * dtype_size(ctx->cfg.storage);
-    if (!ctx->apply_in) HIP_TRY(hipMalloc(&ctx->apply_in, bytes));
-    if (!ctx->apply_out) HIP_TRY(hipMalloc(&ctx->apply_out, bytes));
+    const size_t bytes = (size_t)ctx->L.total * dtype_size(ctx->cfg.storage);
+    if (!ctx->apply_in) {
+        HIP_TRY(hipMalloc(&ctx->apply_in, bytes));
+        HIP_TRY(hipMemsetAsync(ctx->apply_in, 0, bytes, ctx->stream));
+    }
+    if (!ctx->apply_out) {
+        HIP_TRY(hipMalloc(&ctx->apply_out, bytes));
+        HIP_TRY(hipMemsetAsync(ctx->apply_out, 0, bytes, ctx->stream));
+    }
     DevState h{};
     h.s = 1.0;
     h.c = 1.0f;
@@ -412,18 +510,37 @@ int sfseg_apply(sfseg_ctx* ctx, const float* x, float* y) {
     *ctx->h_st = h;
     HIP_TRY(hipMemcpyAsync(ctx->st_apply, ctx->h_st, sizeof(DevState), hipMemcpyHostToDevice,
                            ctx->stream));
-    HIP_TRY(sfseg::launch_to_storage(ctx->cfg.storage, x, ctx->apply_in, ctx->n, ctx->ew_grid,
+    HIP_TRY(sfseg::launch_to_storage(ctx->cfg.storage, x, ctx->apply_in, ctx->L, ctx->ew_grid,
                                      ctx->stream));
     StepParams p = ctx->params[0];
     p.x = ctx->apply_in;
     p.y = ctx->apply_out;
     p.st = ctx->st_apply;
-    HIP_TRY(sfseg::launch_step(ctx->cfg.storage, ctx->cfg.r_s, ctx->cfg.r_t, p, ctx->step_grid,
-                               ctx->stream));
-    HIP_TRY(sfseg::launch_from_storage(ctx->cfg.storage, ctx->apply_out, y, ctx->n, ctx->ew_grid,
+    HIP_TRY(sfseg::launch_step(ctx->cfg.storage, ctx->shape, ctx->cfg.r_s, ctx->cfg.r_t, p,
+                               ctx->step_grid, ctx->stream));
+    HIP_TRY(sfseg::launch_from_storage(ctx->cfg.storage, ctx->apply_out, y, ctx->L, ctx->ew_grid,
                                        ctx->stream));
     HIP_TRY(hipStreamSynchronize(ctx->stream));
     return SFSEG_OK;
+}
+
+int sfseg_get_plan(const sfseg_ctx* ctx, sfseg_plan* out) {
+    if (!ctx || !out) return fail(SFSEG_ERR_INVALID_ARG, "ctx or out is NULL");
+    out->shape = ctx->shape;
+    out->chunks = ctx->chunks;
+    out->blocks = ctx->step_grid;
+    out->threads = sfseg::step_threads(ctx->shape);
+    return SFSEG_OK;
+}
+
+int sfseg_set_plan(sfseg_ctx* ctx, int32_t shape, int32_t chunks) {
+    if (!ctx) return fail(SFSEG_ERR_INVALID_ARG, "ctx is NULL");
+    if (shape < 0 || shape >= sfseg::STEP_SHAPES)
+        return fail(SFSEG_ERR_INVALID_ARG, "shape must be 0..%d", sfseg::STEP_SHAPES - 1);
+    if (chunks < 1 || chunks > max_chunks(ctx->cfg))
+        return fail(SFSEG_ERR_INVALID_ARG, "chunks must be 1..%d for this clip", max_chunks(ctx->cfg));
+    HIP_TRY(hipSetDevice(ctx->device));
+    return install_plan(ctx, shape, chunks);
 }
 
 int sfseg_last_timing(const sfseg_ctx* ctx, sfseg_timing* out) {

@@ -31,43 +31,62 @@ struct DevState {
     int32_t pad;
 };
 
+// Zero-padded storage layout of every internal volume: frames of Hp x Wp
+// elements with the H x W picture at row PT and column PL.  Tiles of
+// TILE_X x TILE_Y cover the picture; the padding holds a full halo around
+// every tile and is never written with anything but zeros.
+struct Layout {
+    int32_t T, H, W;
+    int32_t Hp, Wp;
+    int32_t PT, PL;
+    int32_t tiles_x, tiles_y;
+    int64_t frame;  // Hp * Wp
+    int64_t total;  // T * frame
+};
+
 // Arguments of the fused step kernel (passed by value).
 struct StepParams {
-    const void* x;  // Y_k, storage dtype, T*H*W
-    const void* w;  // S^p, storage dtype
-    const void* f;  // F, storage dtype
-    void* y;        // Y_{k+1}, storage dtype
+    const void* x;  // Y_k, storage dtype, padded layout
+    const void* w;  // S^p
+    const void* f;  // F
+    void* y;        // Y_{k+1}
     DevState* st;
-    double* partials;  // 2 doubles per block
-    int32_t T, H, W;
-    int32_t tiles_x, tiles_y;
-    int64_t n_units;  // tiles_x * tiles_y * T  (tile-major, frame-minor work units)
+    double* partials;    // 2 doubles per block
+    const int4* items;   // per logical block: tile origin x, y (picture coords), frames [z, w)
+    int32_t T, Wp, PT, PL;
+    int64_t frame;
     float gs[SFSEG_MAX_RS + 1];  // spatial taps g_s[d], d = 0..r_s
     float gt[SFSEG_MAX_RT + 1];  // temporal taps g_t[d], d = 0..r_t
     float alpha;
 };
 
 // Output tile of one block and frame: TILE_X columns x TILE_Y rows.
-constexpr int STEP_THREADS = 256;
 constexpr int TILE_X = 64;
 constexpr int TILE_Y = 16;
+// Block shapes of the step kernel: 0 = 256 threads, 4 outputs each along x;
+// 1 = 512 threads, 2 outputs each.
+constexpr int STEP_SHAPES = 2;
+constexpr int step_threads(int shape) { return shape == 0 ? 256 : 512; }
 
-hipError_t launch_step(int dtype, int rs, int rt, const StepParams& p, int grid,
+hipError_t launch_step(int dtype, int shape, int rs, int rt, const StepParams& p, int grid,
                        hipStream_t stream);
-hipError_t step_max_blocks_per_cu(int dtype, int rs, int rt, int* blocks);
+hipError_t step_max_blocks_per_cu(int dtype, int shape, int rs, int rt, int* blocks);
 
+// Element-wise kernels between unpadded float32 volumes (the ABI) and padded
+// storage volumes (the library's internal layout).
 hipError_t launch_prep(int dtype, const float* S, const float* F, double p, void* w, void* f,
-                       void* s0, int64_t n, int32_t* bad_flag, int grid, hipStream_t stream);
+                       void* s0, const Layout& L, int32_t* bad_flag, int grid,
+                       hipStream_t stream);
 // Copy the start vector into Y_0 (storage dtype) and set up the state.
-// src_is_storage: src points to a storage-dtype volume (the kept copy of S)
-// rather than float32.
-hipError_t launch_init(int dtype, const void* src, int src_is_storage, void* y0, int64_t n,
+// src_is_storage: src is a padded storage volume (the kept copy of S) rather
+// than an unpadded float32 volume.
+hipError_t launch_init(int dtype, const void* src, int src_is_storage, void* y0, const Layout& L,
                        DevState* st, double* partials, int grid, hipStream_t stream);
-hipError_t launch_eigvec(int dtype, const void* y, const DevState* st, float* out, int64_t n,
-                         int grid, hipStream_t stream);
-hipError_t launch_to_storage(int dtype, const float* src, void* dst, int64_t n, int grid,
+hipError_t launch_eigvec(int dtype, const void* y, const DevState* st, float* out,
+                         const Layout& L, int grid, hipStream_t stream);
+hipError_t launch_to_storage(int dtype, const float* src, void* dst, const Layout& L, int grid,
                              hipStream_t stream);
-hipError_t launch_from_storage(int dtype, const void* src, float* dst, int64_t n, int grid,
+hipError_t launch_from_storage(int dtype, const void* src, float* dst, const Layout& L, int grid,
                                hipStream_t stream);
 
 }  // namespace sfseg

@@ -1,26 +1,36 @@
-// gfx950 kernels of the SFSeg power iteration.
+// Fused power-iteration step for gfx950.
 //
-// One power-iteration step (Eq. (4) then Eq. (8)) is one launch of the fused
-// step kernel.  The adjacency of Eq. (2) is applied through its three-filter
-// form (Eq. (7), multiplied out by alpha so that alpha = 0 needs no special
-// case):
+// One power-iteration step (Eq. (4) then Eq. (8)) is one launch of this
+// kernel.  The adjacency of Eq. (2) is applied through its three-filter form
+// (Eq. (7), multiplied out by alpha so that alpha = 0 needs no special case):
 //
 //     u = w * x,   A = G * u,   B = G * (F^2 u),   C = G * (F u)
 //     y = w * [ A - alpha * (F * (F * A - 2 C) + B) ]
 //
 // with G the separable box-truncated Gaussian of Eq. (1) (Sec. 4.2: a 3D
-// filter is three 1D filters) and zero padding at the volume faces, which
-// is what makes the filtering equal the symmetric matrix M.
+// filter is three 1D filters) and zero padding at the volume faces, which is
+// what makes the filtering equal the symmetric matrix M.
 //
-// Work layout of the step kernel: the volume is cut into 64 x 16 pixel
-// tiles; the (tile, frame) units are laid out tile-major and split into equal
-// contiguous ranges, one per block, so every block does the same work.  A
-// block streams along time through its range: for each input frame it loads
-// the tile plus an r_s halo, forms the three fields, filters them along y
-// (LDS -> LDS) and x (LDS -> registers), and pushes the result into a
-// register ring of 2 r_t + 1 frames; once the ring holds frames
-// t - r_t .. t + r_t it filters along t, combines, stores frame t and
-// accumulates sum(y^2) and sum(y * Y_k) in float64 on the stored values.  The
+// Memory layout.  Every volume the kernel touches is stored zero-padded: each
+// frame is Hp x Wp with the H x W picture at row PT = r_s, column PL (a
+// multiple of 4 >= r_s), so that a tile's halo never leaves the frame and
+// needs no bounds test.  Outputs that fall in the padding are exactly zero
+// (w = 0 there), so they are stored and summed like any other.
+//
+// Work layout.  A block owns one 64 x 16 pixel tile over a run of frames (one
+// work item).  Items are ordered chunk by chunk and, inside a chunk, tile row
+// by tile row; blocks are dealt to the 8 XCDs round-robin, so the block index
+// is remapped to give each XCD a contiguous run of items: neighbouring tiles
+// then stream the same frames at the same time on the same L2, and the halo
+// each one loads is the neighbour's interior, already cached.
+//
+// Per input frame a block loads the tile plus an r_s halo as column strips
+// (raw buffer loads, prefetched one frame ahead), forms the three fields in
+// registers, filters them along y into LDS and along x back into registers,
+// and pushes the result into a register ring of 2 r_t + 1 frames; once the
+// ring holds frames t - r_t .. t + r_t it filters along t, combines, stores
+// frame t and accumulates sum(y^2) and sum(y * Y_k) in float64 on the stored
+// values.  The
 // block's partial sums go to memory; the last block to finish reduces all
 // partials in a fixed order and advances the iteration state (norm, Rayleigh
 // quotient, change, convergence flag), so results are bit-reproducible.
@@ -37,11 +47,44 @@
 namespace sfseg {
 namespace detail {
 
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+constexpr int kBufferFlags = 0x00020000;  // raw (untyped) buffer, 32-bit lanes
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes,
+                                             kBufferFlags);
+}
 
 // ---------------------------------------------------------------------------
-// Storage precisions: float32, bfloat16, float16 (values are widened to
-// float32 on load; float32 results are rounded to nearest-even on store).
+// Storage precisions: float32, bfloat16, float16.  Values are widened to
+// float32 on load; float32 results are rounded to nearest-even on store.
 // ---------------------------------------------------------------------------
+// N (2 or 4) consecutive 16-bit values: loads of 2N bytes; stores take values
+// already rounded to the storage type.
+#define SFSEG_HALF_VECTOR_IO                                                                  \
+    template <int N>                                                                          \
+    static __device__ __forceinline__ void bloadn(__amdgpu_buffer_rsrc_t r, int off, float* v) { \
+        if constexpr (N == 4) {                                                               \
+            const u32x2 d = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);               \
+            v[0] = widen(d.x & 0xffffu); v[1] = widen(d.x >> 16);                             \
+            v[2] = widen(d.y & 0xffffu); v[3] = widen(d.y >> 16);                             \
+        } else {                                                                              \
+            const uint32_t d = __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);            \
+            v[0] = widen(d & 0xffffu); v[1] = widen(d >> 16);                                 \
+        }                                                                                     \
+    }                                                                                         \
+    template <int N>                                                                          \
+    static __device__ __forceinline__ void bstoren(__amdgpu_buffer_rsrc_t r, int off,         \
+                                                   const float* v) {                          \
+        if constexpr (N == 4) {                                                               \
+            u32x2 d = {bits(v[0]) | (bits(v[1]) << 16), bits(v[2]) | (bits(v[3]) << 16)};     \
+            __builtin_amdgcn_raw_buffer_store_b64(d, r, off, 0, 0);                           \
+        } else {                                                                              \
+            __builtin_amdgcn_raw_buffer_store_b32(bits(v[0]) | (bits(v[1]) << 16), r, off, 0, 0); \
+        }                                                                                     \
+    }
+
 template <typename TS>
 struct Stor;
 template <>
@@ -49,20 +92,82 @@ struct Stor<float> {
     static __device__ __forceinline__ float ld(const float* p, int64_t i) { return p[i]; }
     static __device__ __forceinline__ float rnd(float v) { return v; }
     static __device__ __forceinline__ void st(float* p, int64_t i, float v) { p[i] = v; }
+    static __device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, int off) {
+        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+    }
+    // voffset (per lane) + soffset (uniform) addressing
+    static __device__ __forceinline__ float bload_s(__amdgpu_buffer_rsrc_t r, int off, int soff) {
+        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, soff, 0));
+    }
+    // N (2 or 4) consecutive values; off is 4N-byte aligned.
+    template <int N>
+    static __device__ __forceinline__ void bloadn(__amdgpu_buffer_rsrc_t r, int off, float* v) {
+        if constexpr (N == 4) {
+            const u32x4 d = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+            v[0] = __uint_as_float(d.x); v[1] = __uint_as_float(d.y);
+            v[2] = __uint_as_float(d.z); v[3] = __uint_as_float(d.w);
+        } else {
+            const u32x2 d = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+            v[0] = __uint_as_float(d.x); v[1] = __uint_as_float(d.y);
+        }
+    }
+    template <int N>
+    static __device__ __forceinline__ void bstoren(__amdgpu_buffer_rsrc_t r, int off,
+                                                   const float* v) {
+        if constexpr (N == 4) {
+            u32x4 d = {__float_as_uint(v[0]), __float_as_uint(v[1]), __float_as_uint(v[2]),
+                       __float_as_uint(v[3])};
+            __builtin_amdgcn_raw_buffer_store_b128(d, r, off, 0, 0);
+        } else {
+            u32x2 d = {__float_as_uint(v[0]), __float_as_uint(v[1])};
+            __builtin_amdgcn_raw_buffer_store_b64(d, r, off, 0, 0);
+        }
+    }
 };
 template <>
 struct Stor<__bf16> {
     static __device__ __forceinline__ float ld(const __bf16* p, int64_t i) { return (float)p[i]; }
     static __device__ __forceinline__ float rnd(float v) { return (float)(__bf16)v; }
     static __device__ __forceinline__ void st(__bf16* p, int64_t i, float v) { p[i] = (__bf16)v; }
+    static __device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, int off) {
+        const unsigned short h = __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0);
+        return __uint_as_float((uint32_t)h << 16);
+    }
+    static __device__ __forceinline__ float bload_s(__amdgpu_buffer_rsrc_t r, int off, int soff) {
+        const unsigned short h = __builtin_amdgcn_raw_buffer_load_b16(r, off, soff, 0);
+        return __uint_as_float((uint32_t)h << 16);
+    }
+    static __device__ __forceinline__ uint32_t bits(float v) {
+        return (uint32_t)__builtin_bit_cast(unsigned short, (__bf16)v);
+    }
+    static __device__ __forceinline__ float widen(uint32_t h) { return __uint_as_float(h << 16); }
+    SFSEG_HALF_VECTOR_IO
 };
 template <>
 struct Stor<_Float16> {
     static __device__ __forceinline__ float ld(const _Float16* p, int64_t i) { return (float)p[i]; }
     static __device__ __forceinline__ float rnd(float v) { return (float)(_Float16)v; }
     static __device__ __forceinline__ void st(_Float16* p, int64_t i, float v) { p[i] = (_Float16)v; }
+    static __device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, int off) {
+        const unsigned short h = __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0);
+        return (float)__builtin_bit_cast(_Float16, h);
+    }
+    static __device__ __forceinline__ float bload_s(__amdgpu_buffer_rsrc_t r, int off, int soff) {
+        const unsigned short h = __builtin_amdgcn_raw_buffer_load_b16(r, off, soff, 0);
+        return (float)__builtin_bit_cast(_Float16, h);
+    }
+    static __device__ __forceinline__ uint32_t bits(float v) {
+        return (uint32_t)__builtin_bit_cast(unsigned short, (_Float16)v);
+    }
+    static __device__ __forceinline__ float widen(uint32_t h) {
+        return (float)__builtin_bit_cast(_Float16, (unsigned short)h);
+    }
+    SFSEG_HALF_VECTOR_IO
 };
 
+// ---------------------------------------------------------------------------
+// Reductions shared by the step and start-vector kernels
+// ---------------------------------------------------------------------------
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -76,8 +181,8 @@ __device__ __forceinline__ void agent_store(double* p, double v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Sum nvals partial values (stride 2 starting at `first`) over nblocks blocks
-// in a fixed order: thread i sums blocks i, i+NT, ...; then a fixed tree.
+// Sum value `first` (0 or 1) of the nblocks partial pairs in a fixed order:
+// thread i sums blocks i, i+NT, ...; then a fixed tree over the threads.
 template <int NT>
 __device__ double fixed_order_sum(const double* partials, int nblocks, int first, double* lds) {
     double acc = 0.0;
@@ -94,7 +199,7 @@ __device__ double fixed_order_sum(const double* partials, int nblocks, int first
     return r;
 }
 
-// Block-wide sum of two doubles into partials[2*slot], partials[2*slot+1];
+// Block-wide sums of a and b written to partials[2*slot], partials[2*slot+1];
 // returns true in every thread of the last block of the launch to arrive.
 template <int NT>
 __device__ bool block_partials_and_ticket(double a, double b, double* partials, int slot,
@@ -161,31 +266,59 @@ __device__ inline void advance_state(DevState* st, double syy, double syx) {
     if (st->k >= st->max_iters) st->done = 1;
 }
 
+// XCD-aware block order: hardware deals block b to XCD b % 8; give XCD x the
+// contiguous logical range [x * G/8, (x+1) * G/8).  G must be a multiple of 8.
+__device__ __forceinline__ int xcd_logical_block(int b, int G) {
+    return (b & 7) * (G >> 3) + (b >> 3);
+}
+
 // ---------------------------------------------------------------------------
 // Fused step kernel
 // ---------------------------------------------------------------------------
-constexpr int NT = STEP_THREADS;
 constexpr int TX = TILE_X, TY = TILE_Y;
-constexpr int PX = 4;              // outputs per thread along x
-constexpr int NSEG = TX / PX;      // 16 thread columns
-constexpr int PY = 4;              // y-pass outputs per work item
-static_assert(NSEG * TY == NT, "one output strip per thread");
+constexpr int round4(int v) { return (v + 3) / 4 * 4; }
 
-template <typename TS, int RS, int RT>
-__global__ __launch_bounds__(NT) void step_kernel(StepParams p) {
-    constexpr int IW = TX + 2 * RS;  // input region (tile + halo) width
-    constexpr int IH = TY + 2 * RS;
-    constexpr int NIN = IW * IH;
-    constexpr int NLD = (NIN + NT - 1) / NT;
-    constexpr int MP = IW | 1;        // odd pitch of the y-filtered rows
-    constexpr int NYI = IW * (TY / PY);
-    constexpr int NYR = (NYI + NT - 1) / NT;
-    constexpr int NR = 2 * RT + 1;    // frames in the time ring
-    constexpr int XW = PX + 2 * RS;   // x-pass register window
-    constexpr int YW = PY + 2 * RS;   // y-pass register window
+// Block shapes: PX outputs per thread along x (so TX / PX thread columns and
+// NT = 16 * TX / PX threads), PY rows per y-pass column strip.
+template <int PX_, int PY_>
+struct Shape {
+    static constexpr int PX = PX_, PY = PY_;
+    static constexpr int NSEG = TX / PX;
+    static constexpr int NT = NSEG * TY;
+    // Minimum waves per SIMD (the second launch-bounds argument): 256-thread
+    // blocks at 2 per CU need 2 (<= 256 VGPRs); 512-thread blocks at 2 per CU
+    // need 4 (<= 128 VGPRs).
+    static constexpr int MINW = NT / 128;
+};
+using ShapeWide = Shape<4, 8>;    // 256 threads
+using ShapeDeep = Shape<2, 4>;    // 512 threads
 
-    __shared__ float in3[3][NIN];     // fields u, F u, F^2 u of the input frame
-    __shared__ float mid3[3][TY * MP];  // y-filtered fields
+// Per input frame a block runs two phases separated by barriers:
+//   Y: each column strip of the tile-plus-halo (64 + 2 r_s columns, 16 / PY
+//      strips per column) loads PY + 2 r_s rows of x, w, F straight from L2
+//      (prefetched one frame ahead), forms the fields u, F u, F^2 u in
+//      registers and filters them along y into LDS;
+//   X: each thread filters a PX-pixel row segment along x (8- or 16-byte LDS
+//      reads that cover the 32 banks without conflicts), pushes it into its
+//      register ring of 2 r_t + 1 frames and, once frame t - r_t's neighbours
+//      are in, filters along t, combines with its own x, w, F (loaded from L2,
+//      prefetched), stores and reduces.
+template <typename TS, int RS, int RT, typename SH>
+__global__ __launch_bounds__(SH::NT, SH::MINW) void step_kernel(StepParams p) {
+    constexpr int NT = SH::NT, PX = SH::PX, PY = SH::PY, NSEG = SH::NSEG;
+    constexpr int IW = TX + 2 * RS;        // strips: tile columns plus halo
+    constexpr int NYS = TY / PY;           // strips per column
+    constexpr int NYI = IW * NYS;          // y-pass strips per frame
+    constexpr int YW = PY + 2 * RS;        // rows loaded per strip
+    constexpr int XWA = round4(PX + 2 * RS);  // x-pass window, whole 8/16-byte reads
+    constexpr int MP = TX - PX + XWA + (PX == 2 ? 2 : 0);  // y-filtered row pitch
+    constexpr int NR = 2 * RT + 1;         // frames in the register ring
+    constexpr int ES = (int)sizeof(TS);
+    static_assert(NYI <= NT, "one strip per thread");
+    static_assert(TY % PY == 0, "whole strips per tile");
+    static_assert(MP % 4 == 0, "aligned rows");
+
+    __shared__ __attribute__((aligned(16))) float mid3[3][TY * MP];  // y-filtered fields
     __shared__ double fin[NT];
 
     DevState* st = p.st;
@@ -204,181 +337,177 @@ __global__ __launch_bounds__(NT) void step_kernel(StepParams p) {
     const TS* __restrict__ Wt = (const TS*)p.w;
     const TS* __restrict__ Fv = (const TS*)p.f;
     TS* __restrict__ Y = (TS*)p.y;
-    const int T = p.T, H = p.H, W = p.W;
-    const int64_t HW = (int64_t)H * W;
+    const int T = p.T, Wp = p.Wp;
+    const int64_t frame = p.frame;  // Hp * Wp elements
+    const uint32_t frame_bytes = (uint32_t)(frame * ES);
+    const int row_bytes = Wp * ES;
 
     const int tid = threadIdx.x;
-    const int orow = tid / NSEG;          // output row inside the tile
-    const int ocol = (tid % NSEG) * PX;   // first output column inside the tile
+    const int orow = tid / NSEG;         // output row inside the tile
+    const int ocol = (tid % NSEG) * PX;  // first output column inside the tile
 
-    // Blocks are dealt to the XCDs round-robin; give each XCD a contiguous
-    // run of ranges so that neighbouring tiles share its L2.
-    const int G = gridDim.x;
-    const int lb = (blockIdx.x % 8) * (G / 8) + blockIdx.x / 8;
-    const int64_t u0 = (int64_t)lb * p.n_units / G;
-    const int64_t u1 = (int64_t)(lb + 1) * p.n_units / G;
+    const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
+    const int4 item = p.items[lb];  // tile origin (picture coords) and frame range
+    const int tx0 = item.x, ty0 = item.y, ta = item.z, tb = item.w;
 
     double syy = 0.0, syx = 0.0;
 
-    for (int64_t u = u0; u < u1;) {
-        const int tile = (int)(u / T);
-        const int ta = (int)(u % T);
-        const int tb = (int)((int64_t)ta + (u1 - u) < T ? (int64_t)ta + (u1 - u) : T);
-        u += tb - ta;
-        const int tx0 = (tile % p.tiles_x) * TX;
-        const int ty0 = (tile / p.tiles_x) * TY;
+    if (tb > ta) {
+        // This thread's y-pass strip: region column ycol, rows yseg*PY .. +YW.
+        const bool yact = tid < NYI;
+        const int ycol = yact ? tid % IW : 0;
+        const int yseg = yact ? tid / IW : 0;
+        // Padded row of window row 0 is ty0 + yseg*PY (PT = r_s), column tx0 + PL - r_s + ycol.
+        const int yoff = ((ty0 + yseg * PY) * Wp + (tx0 + p.PL - RS + ycol)) * ES;
+        const int ooff = ((ty0 + p.PT + orow) * Wp + (tx0 + p.PL + ocol)) * ES;
 
-        // In-frame offsets of this thread's input-region elements (-1: outside).
-        int goff[NLD];
+        // Frames outside the clip read as zeros: their descriptor has no valid
+        // bytes (and points at frame 0, so even an unchecked access stays inside
+        // the volume).
+        auto rsrc = [&](const TS* base, int t) {
+            const bool tin = t >= 0 && t < T;
+            return make_rsrc(base + (tin ? (int64_t)t * frame : 0), tin ? frame_bytes : 0u);
+        };
+        float pX[YW], pW[YW], pF[YW];  // prefetched strip of the next frame
+        float qX[PX], qW[PX], qF[PX];  // prefetched own x, w, F of the next output frame
 #pragma unroll
-        for (int m = 0; m < NLD; ++m) {
-            const int e = tid + m * NT;
-            const int r = e / IW, cc = e - (e / IW) * IW;
-            const int gy = ty0 - RS + r, gx = tx0 - RS + cc;
-            goff[m] = (e < NIN && gy >= 0 && gy < H && gx >= 0 && gx < W) ? gy * W + gx : -1;
-        }
-        const int gyo = ty0 + orow;
-        const int gxo = tx0 + ocol;
-        const bool orow_ok = gyo < H;
-
-        float pX[NLD], pW[NLD], pF[NLD];  // prefetched input region of the next frame
-        float cX[PX], cW[PX], cF[PX];     // prefetched own outputs' x, w, F
-        auto load_frame = [&](int t) {
-            const bool tin = (t >= 0 && t < T);
-            const int64_t base = (int64_t)t * HW;
+        for (int k = 0; k < YW; ++k) pX[k] = pW[k] = pF[k] = 0.f;
+        auto load_strip = [&](int t) {
+            const __amdgpu_buffer_rsrc_t rx = rsrc(X, t), rw = rsrc(Wt, t), rf = rsrc(Fv, t);
+            if (yact) {
 #pragma unroll
-            for (int m = 0; m < NLD; ++m) {
-                const bool ok = tin && goff[m] >= 0;
-                const int64_t i = base + (ok ? goff[m] : 0);
-                pX[m] = ok ? Stor<TS>::ld(X, i) : 0.f;
-                pW[m] = ok ? Stor<TS>::ld(Wt, i) : 0.f;
-                pF[m] = ok ? Stor<TS>::ld(Fv, i) : 0.f;
-            }
-#pragma unroll
-            for (int i = 0; i < PX; ++i) {
-                const bool ok = tin && orow_ok && (gxo + i) < W;
-                const int64_t j = base + (ok ? (int64_t)gyo * W + gxo + i : 0);
-                cX[i] = ok ? Stor<TS>::ld(X, j) : 0.f;
-                cW[i] = ok ? Stor<TS>::ld(Wt, j) : 0.f;
-                cF[i] = ok ? Stor<TS>::ld(Fv, j) : 0.f;
+                for (int k = 0; k < YW; ++k) {
+                    pX[k] = Stor<TS>::bload_s(rx, yoff, k * row_bytes);
+                    pW[k] = Stor<TS>::bload_s(rw, yoff, k * row_bytes);
+                    pF[k] = Stor<TS>::bload_s(rf, yoff, k * row_bytes);
+                }
             }
         };
+        auto load_own = [&](int t) {
+            const __amdgpu_buffer_rsrc_t rx = rsrc(X, t), rw = rsrc(Wt, t), rf = rsrc(Fv, t);
+            Stor<TS>::template bloadn<PX>(rx, ooff, qX);
+            Stor<TS>::template bloadn<PX>(rw, ooff, qW);
+            Stor<TS>::template bloadn<PX>(rf, ooff, qF);
+        };
 
-        float ring[NR][3][PX];   // x/y-filtered fields of the last NR frames
-        float cring[NR][3][PX];  // x, w, F of this thread's outputs, same frames
+        float ring[NR][3][PX];  // x/y-filtered fields of the last NR frames
 #pragma unroll
         for (int j = 0; j < NR; ++j)
 #pragma unroll
             for (int f = 0; f < 3; ++f)
 #pragma unroll
-                for (int i = 0; i < PX; ++i) ring[j][f][i] = cring[j][f][i] = 0.f;
+                for (int i = 0; i < PX; ++i) ring[j][f][i] = 0.f;
 
-        const int n_in = (tb - ta) + 2 * RT;  // input frames ta-RT .. tb+RT-1
-        load_frame(ta - RT);
+        // Input frames ta-RT .. tb+RT-1, rounded up to whole ring turns; the
+        // extra steps read frames past the run and store nothing.
+        const int n_in = (tb - ta) + 2 * RT;
+        const int n_steps = (n_in + NR - 1) / NR * NR;
+        load_strip(ta - RT);
+        load_own(ta);
 
-        for (int s0 = 0; s0 < n_in; s0 += NR) {
+        for (int s0 = 0; s0 < n_steps; s0 += NR) {
 #pragma unroll
             for (int j = 0; j < NR; ++j) {
                 const int s = s0 + j;
-                if (s < n_in) {
-                    const int t_in = ta - RT + s;
-                    __syncthreads();  // previous frame's readers of in3 / mid3 are done
-                    // (1) fields of frame t_in into LDS
+                const int t_in = ta - RT + s;
+                // ---- Y phase: fields, prefetch of the next strip, filter along y ----
+                // The 256-thread shape has the registers to issue the next
+                // strip's loads before filtering; the 512-thread shape (128
+                // VGPRs) turns the strip into the fields in place and loads
+                // after filtering.
+                if (yact) {
+                    constexpr bool early = NT == 256;
+                    float fu[YW], fv[YW], fz[YW];
 #pragma unroll
-                    for (int m = 0; m < NLD; ++m) {
-                        const int e = tid + m * NT;
-                        if (e < NIN) {
-                            const float uu = pW[m] * pX[m];
-                            const float vv = pF[m] * uu;
-                            in3[0][e] = uu;
-                            in3[1][e] = vv;
-                            in3[2][e] = pF[m] * vv;
+                    for (int k = 0; k < YW; ++k) {
+                        fu[k] = pW[k] * pX[k];
+                        fv[k] = pF[k] * fu[k];
+                        fz[k] = pF[k] * fv[k];
+                    }
+                    if constexpr (early) load_strip(t_in + 1);
+#pragma unroll
+                    for (int i = 0; i < PY; ++i) {
+                        float a0 = gs[0] * fu[i + RS], a1 = gs[0] * fv[i + RS],
+                              a2 = gs[0] * fz[i + RS];
+#pragma unroll
+                        for (int d = 1; d <= RS; ++d) {
+                            a0 = fmaf(gs[d], fu[i + RS - d] + fu[i + RS + d], a0);
+                            a1 = fmaf(gs[d], fv[i + RS - d] + fv[i + RS + d], a1);
+                            a2 = fmaf(gs[d], fz[i + RS - d] + fz[i + RS + d], a2);
+                        }
+                        const int o = (yseg * PY + i) * MP + ycol;
+                        mid3[0][o] = a0;
+                        mid3[1][o] = a1;
+                        mid3[2][o] = a2;
+                    }
+                    if constexpr (!early) load_strip(t_in + 1);
+                }
+                __syncthreads();
+                // ---- X phase: filter along x into ring slot j ----
+#pragma unroll
+                for (int f = 0; f < 3; ++f) {
+                    float win[XWA];
+                    const float* src = &mid3[f][orow * MP + ocol];
+                    if constexpr (PX % 4 == 0) {
+#pragma unroll
+                        for (int q = 0; q < XWA / 4; ++q) {
+                            const float4 v4 = reinterpret_cast<const float4*>(src)[q];
+                            win[4 * q + 0] = v4.x;
+                            win[4 * q + 1] = v4.y;
+                            win[4 * q + 2] = v4.z;
+                            win[4 * q + 3] = v4.w;
+                        }
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < XWA / 2; ++q) {
+                            const float2 v2 = reinterpret_cast<const float2*>(src)[q];
+                            win[2 * q + 0] = v2.x;
+                            win[2 * q + 1] = v2.y;
                         }
                     }
 #pragma unroll
                     for (int i = 0; i < PX; ++i) {
-                        cring[j][0][i] = cX[i];
-                        cring[j][1][i] = cW[i];
-                        cring[j][2][i] = cF[i];
-                    }
-                    // (2) prefetch the next frame while this one is filtered
-                    if (s + 1 < n_in) load_frame(t_in + 1);
-                    __syncthreads();
-                    // (3) filter along y: in3 -> mid3
+                        float a = gs[0] * win[i + RS];
 #pragma unroll
-                    for (int m = 0; m < NYR; ++m) {
-                        const int it = tid + m * NT;
-                        if (it < NYI) {
-                            const int col = it % IW;
-                            const int r0 = (it / IW) * PY;
-#pragma unroll
-                            for (int f = 0; f < 3; ++f) {
-                                float win[YW];
-#pragma unroll
-                                for (int k = 0; k < YW; ++k) win[k] = in3[f][(r0 + k) * IW + col];
-#pragma unroll
-                                for (int i = 0; i < PY; ++i) {
-                                    float a = gs[0] * win[i + RS];
-#pragma unroll
-                                    for (int d = 1; d <= RS; ++d)
-                                        a = fmaf(gs[d], win[i + RS - d] + win[i + RS + d], a);
-                                    mid3[f][(r0 + i) * MP + col] = a;
-                                }
-                            }
-                        }
-                    }
-                    __syncthreads();
-                    // (4) filter along x: mid3 -> ring slot j
-#pragma unroll
-                    for (int f = 0; f < 3; ++f) {
-                        float win[XW];
-#pragma unroll
-                        for (int k = 0; k < XW; ++k) win[k] = mid3[f][orow * MP + ocol + k];
-#pragma unroll
-                        for (int i = 0; i < PX; ++i) {
-                            float a = gs[0] * win[i + RS];
-#pragma unroll
-                            for (int d = 1; d <= RS; ++d)
-                                a = fmaf(gs[d], win[i + RS - d] + win[i + RS + d], a);
-                            ring[j][f][i] = a;
-                        }
-                    }
-                    // (5) once frames t-RT..t+RT are in the ring: filter along t,
-                    //     combine (Eq. (7)), store frame t = t_in - RT, reduce.
-                    if (s >= 2 * RT) {
-                        const int t_out = t_in - RT;
-                        const int jc = (j + NR - RT) % NR;  // ring slot of frame t_out (constant once unrolled)
-                        const int64_t obase = (int64_t)t_out * HW + (int64_t)gyo * W + gxo;
-#pragma unroll
-                        for (int i = 0; i < PX; ++i) {
-                            float A = 0.f, B = 0.f, C = 0.f;
-#pragma unroll
-                            for (int m = 0; m < NR; ++m) {
-                                const int slot = (j + 1 + m) % NR;
-                                A = fmaf(gt[m], ring[slot][0][i], A);  // G * u
-                                C = fmaf(gt[m], ring[slot][1][i], C);  // G * (F u)
-                                B = fmaf(gt[m], ring[slot][2][i], B);  // G * (F^2 u)
-                            }
-                            const float xc = cring[jc][0][i];
-                            const float wc = cring[jc][1][i];
-                            const float fc = cring[jc][2][i];
-                            const float E = fmaf(-alpha, fmaf(fc, fmaf(fc, A, -2.f * C), B), A);
-                            const float yq = Stor<TS>::rnd(wc * E);
-                            if (orow_ok && gxo + i < W) {
-                                Stor<TS>::st(Y, obase + i, yq);
-                                syy = fma((double)yq, (double)yq, syy);
-                                syx = fma((double)yq, (double)xc, syx);
-                            }
-                        }
+                        for (int d = 1; d <= RS; ++d)
+                            a = fmaf(gs[d], win[i + RS - d] + win[i + RS + d], a);
+                        ring[j][f][i] = a;
                     }
                 }
+                // ---- once frames t-RT..t+RT are in: filter along t, combine
+                //      (Eq. (7)), store frame t = t_in - RT, reduce ----
+                const int t_out = t_in - RT;
+                if (t_out >= ta && t_out < tb) {
+                    float yv[PX];
+#pragma unroll
+                    for (int i = 0; i < PX; ++i) {
+                        float A = 0.f, B = 0.f, C = 0.f;
+#pragma unroll
+                        for (int m = 0; m < NR; ++m) {
+                            const int slot = (j + 1 + m) % NR;  // constant once unrolled
+                            A = fmaf(gt[m], ring[slot][0][i], A);  // G * u
+                            C = fmaf(gt[m], ring[slot][1][i], C);  // G * (F u)
+                            B = fmaf(gt[m], ring[slot][2][i], B);  // G * (F^2 u)
+                        }
+                        const float E = fmaf(-alpha, fmaf(qF[i], fmaf(qF[i], A, -2.f * C), B), A);
+                        const float yq = Stor<TS>::rnd(qW[i] * E);
+                        yv[i] = yq;
+                        syy = fma((double)yq, (double)yq, syy);
+                        syx = fma((double)yq, (double)qX[i], syx);
+                    }
+                    const __amdgpu_buffer_rsrc_t ry =
+                        make_rsrc(Y + (int64_t)t_out * frame, frame_bytes);
+                    Stor<TS>::template bstoren<PX>(ry, ooff, yv);
+                    load_own(t_out + 1);
+                }
+                __syncthreads();  // mid3 is free again
             }
         }
     }
 
-    if (block_partials_and_ticket<NT>(syy, syx, p.partials, lb, &st->ticket, (uint32_t)G)) {
-        const double tyy = fixed_order_sum<NT>(p.partials, G, 0, fin);
-        const double tyx = fixed_order_sum<NT>(p.partials, G, 1, fin);
+    if (block_partials_and_ticket<NT>(syy, syx, p.partials, lb, &st->ticket, (uint32_t)gridDim.x)) {
+        const double tyy = fixed_order_sum<NT>(p.partials, gridDim.x, 0, fin);
+        const double tyx = fixed_order_sum<NT>(p.partials, gridDim.x, 1, fin);
         if (threadIdx.x == 0) {
             advance_state(st, tyy, tyx);
             __hip_atomic_store(&st->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -386,37 +515,41 @@ __global__ __launch_bounds__(NT) void step_kernel(StepParams p) {
     }
 }
 
-
-// Launch / occupancy tables over (r_s, r_t) for one storage type.
-template <typename TS, int RS, int RT>
+// Launch / occupancy tables over (shape, r_s, r_t) for one storage type.
+template <typename TS, int RS, int RT, typename SH>
 hipError_t launch_step_t(const StepParams& p, int grid, hipStream_t s) {
-    hipLaunchKernelGGL((step_kernel<TS, RS, RT>), dim3(grid), dim3(NT), 0, s, p);
+    hipLaunchKernelGGL((step_kernel<TS, RS, RT, SH>), dim3(grid), dim3(SH::NT), 0, s, p);
     return hipGetLastError();
 }
-template <typename TS, int RS, int RT>
+template <typename TS, int RS, int RT, typename SH>
 hipError_t occ_step_t(int* blocks) {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, step_kernel<TS, RS, RT>, NT, 0);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, step_kernel<TS, RS, RT, SH>,
+                                                        SH::NT, 0);
 }
 
 using LaunchFn = hipError_t (*)(const StepParams&, int, hipStream_t);
 using OccFn = hipError_t (*)(int*);
+constexpr int NSHAPES = 2;  // 0: ShapeWide (256 threads), 1: ShapeDeep (512 threads)
 constexpr int NCOMB = (SFSEG_MAX_RS + 1) * (SFSEG_MAX_RT + 1);
 
-template <typename TS, int RS, int... RTs>
+template <typename TS, typename SH, int RS, int... RTs>
 void fill_rt(LaunchFn* lt, OccFn* ot, std::integer_sequence<int, RTs...>) {
-    ((lt[RS * (SFSEG_MAX_RT + 1) + RTs] = &launch_step_t<TS, RS, RTs>,
-      ot[RS * (SFSEG_MAX_RT + 1) + RTs] = &occ_step_t<TS, RS, RTs>), ...);
+    ((lt[RS * (SFSEG_MAX_RT + 1) + RTs] = &launch_step_t<TS, RS, RTs, SH>,
+      ot[RS * (SFSEG_MAX_RT + 1) + RTs] = &occ_step_t<TS, RS, RTs, SH>), ...);
 }
-template <typename TS, int... RSs>
+template <typename TS, typename SH, int... RSs>
 void fill_rs(LaunchFn* lt, OccFn* ot, std::integer_sequence<int, RSs...>) {
-    (fill_rt<TS, RSs>(lt, ot, std::make_integer_sequence<int, SFSEG_MAX_RT + 1>{}), ...);
+    (fill_rt<TS, SH, RSs>(lt, ot, std::make_integer_sequence<int, SFSEG_MAX_RT + 1>{}), ...);
 }
 
 template <typename TS>
 struct StepTable {
-    LaunchFn launch[NCOMB];
-    OccFn occ[NCOMB];
-    StepTable() { fill_rs<TS>(launch, occ, std::make_integer_sequence<int, SFSEG_MAX_RS + 1>{}); }
+    LaunchFn launch[NSHAPES][NCOMB];
+    OccFn occ[NSHAPES][NCOMB];
+    StepTable() {
+        fill_rs<TS, ShapeWide>(launch[0], occ[0], std::make_integer_sequence<int, SFSEG_MAX_RS + 1>{});
+        fill_rs<TS, ShapeDeep>(launch[1], occ[1], std::make_integer_sequence<int, SFSEG_MAX_RS + 1>{});
+    }
 };
 
 }  // namespace detail

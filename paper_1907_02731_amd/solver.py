@@ -135,6 +135,17 @@ class Solver:
             torch.cuda.current_stream().wait_stream(self.stream)
         return out
 
+    def plan(self) -> dict:
+        pl = _lib.Plan()
+        _lib.check(_lib.lib().sfseg_get_plan(self._handle(), ctypes.byref(pl)), "sfseg_get_plan")
+        return {"shape": int(pl.shape), "chunks": int(pl.chunks), "blocks": int(pl.blocks),
+                "threads": int(pl.threads)}
+
+    def set_plan(self, shape: int, chunks: int) -> None:
+        with torch.cuda.device(self.device):
+            _lib.check(_lib.lib().sfseg_set_plan(self._handle(), int(shape), int(chunks)),
+                       "sfseg_set_plan")
+
     def timing(self) -> dict:
         t = _lib.Timing()
         _lib.check(_lib.lib().sfseg_last_timing(self._handle(), ctypes.byref(t)),

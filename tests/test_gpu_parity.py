@@ -291,3 +291,36 @@ def test_full_converged_invariants(full):
     lam = x @ y
     assert abs(res.lam - lam) <= 1e-5 * lam
     assert np.linalg.norm(y - lam * x) / lam <= 10 * res.delta + 1e-6
+
+
+@pytest.fixture(scope="module")
+def long_clip():
+    # 24 frames: up to 3 runs of frames per tile with r_t = 1
+    S = make_clip(24, 40, 70, seed=24, n_blobs=2, noise_sigma=0.1, motion="drift",
+                  dtype=np.float32)
+    return S, build_adjacency(S.astype(np.float64), None, TINY)
+
+
+@pytest.mark.parametrize("shape,chunks", [(0, 1), (1, 1), (0, 2), (1, 3)])
+def test_every_plan_gives_the_same_trajectory(long_clip, shape, chunks):
+    S, M = long_clip
+    with _solver(S) as sol:
+        sol.set_plan(shape, chunks)
+        pl = sol.plan()
+        assert (pl["shape"], pl["chunks"]) == (shape, chunks)
+        assert pl["blocks"] % 8 == 0 and pl["threads"] == (256 if shape == 0 else 512)
+        y = _f64(sol.apply(_t(S)))
+        sol.iterate(max_iters=30, tol=0.0)
+        x = _f64(sol.eigvec()).ravel()
+    _check_apply(y, M @ S.astype(np.float64).ravel())
+    ref = power_iteration(lambda v: M @ v, S.astype(np.float64).ravel(), 30, 0.0)
+    assert np.linalg.norm(x - ref["x"]) <= 1e-5
+
+
+def test_plan_rejects_bad_values(tiny):
+    S, _ = tiny
+    with _solver(S) as sol:
+        for shape, chunks in ((2, 1), (-1, 1), (0, 0), (0, 10_000)):
+            with pytest.raises(_lib.SfsegError) as e:
+                sol.set_plan(shape, chunks)
+            assert e.value.status == _lib.SFSEG_ERR_INVALID_ARG
