@@ -53,6 +53,10 @@ def parse():
                     help="run exactly this many steps per solve (tol = 0); for profiling")
     ap.add_argument("--shape", type=int, default=-1, help="step-kernel block shape (0/1)")
     ap.add_argument("--chunks", type=int, default=0, help="frame runs per tile")
+    ap.add_argument("--precision-report", action="store_true",
+                    help="for 16-bit storage: error of the final iterate against the float32 "
+                         "result after the same number of steps, and the FP64 oracle's residual "
+                         "||Mx - lambda x|| / lambda for both")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=20,
                     help="oracle power-iteration steps timed for the CPU baseline")
@@ -72,6 +76,38 @@ def cpu_baseline(S, cfg_o, steps):
             "kind": "oracle",
             "sample": f"{steps} FP64 power-iteration steps of the matrix-free oracle on the "
                       f"whole {'x'.join(map(str, S.shape))} clip ({dt:.1f} s)"}
+
+
+def precision_report(S, St, kw, K, x_lo):
+    """Error of a 16-bit-storage iterate: against float32 storage after the same
+    K steps, and the FP64 oracle's relative residual of each vector."""
+    import torch
+
+    from oracle import OracleConfig
+    from oracle.native import MatrixFree
+    from paper_1907_02731_amd.solver import Solver
+
+    kw32 = dict(kw, storage="f32")
+    with Solver(St, **kw32) as ref:
+        ref.iterate(max_iters=K, tol=0.0)
+        x32 = ref.eigvec().cpu().numpy().astype(np.float64).ravel()
+    xl = x_lo.cpu().numpy().astype(np.float64).ravel()
+    cfg = OracleConfig(r_t=kw["r_t"], r_s=kw["r_s"], sigma_t=kw["sigma_t"],
+                       sigma_s=kw["sigma_s"], alpha=kw["alpha"], p=kw["p"])
+    mf = MatrixFree(S, None, cfg)
+
+    def residual(x):
+        y = mf.apply(x)
+        lam = float(x @ y)
+        return float(np.linalg.norm(y - lam * x) / lam), lam
+
+    r32, l32 = residual(x32)
+    rlo, llo = residual(xl)
+    return {"storage": kw["storage"], "steps": K,
+            "rel_l2_vs_f32": float(np.linalg.norm(xl - x32) / np.linalg.norm(x32)),
+            "max_abs_vs_f32": float(np.max(np.abs(xl - x32))),
+            "oracle_residual_f32": r32, "oracle_residual": rlo,
+            "oracle_rayleigh_f32": l32, "oracle_rayleigh": llo}
 
 
 def main():
@@ -166,6 +202,8 @@ def main():
             "bytes_per_launch": bytes_per_launch,
         },
     }
+    if args.precision_report:
+        line["precision"] = precision_report(S, St, kw, max(iters), out)
     if not args.no_cpu_baseline:
         from oracle import OracleConfig
         cfg_o = OracleConfig(r_t=r_t, r_s=r_s, sigma_t=s_t, sigma_s=s_s, alpha=args.alpha,

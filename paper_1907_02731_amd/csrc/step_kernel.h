@@ -293,7 +293,8 @@ struct Shape {
 using ShapeWide = Shape<4, 8>;    // 256 threads
 using ShapeDeep = Shape<2, 4>;    // 512 threads
 
-// Per input frame a block runs two phases separated by barriers:
+// Per input frame a block runs two phases, software-pipelined so that the y
+// phase of frame t+1 shares a barrier interval with the x phase of frame t:
 //   Y: each column strip of the tile-plus-halo (64 + 2 r_s columns, 16 / PY
 //      strips per column) loads PY + 2 r_s rows of x, w, F straight from L2
 //      (prefetched one frame ahead), forms the fields u, F u, F^2 u in
@@ -318,7 +319,7 @@ __global__ __launch_bounds__(SH::NT, SH::MINW) void step_kernel(StepParams p) {
     static_assert(TY % PY == 0, "whole strips per tile");
     static_assert(MP % 4 == 0, "aligned rows");
 
-    __shared__ __attribute__((aligned(16))) float mid3[3][TY * MP];  // y-filtered fields
+    __shared__ __attribute__((aligned(16))) float mid3[2][3][TY * MP];  // y-filtered fields, double-buffered
     __shared__ double fin[NT];
 
     DevState* st = p.st;
@@ -398,56 +399,63 @@ __global__ __launch_bounds__(SH::NT, SH::MINW) void step_kernel(StepParams p) {
 #pragma unroll
                 for (int i = 0; i < PX; ++i) ring[j][f][i] = 0.f;
 
+        // Y phase of input step q (frame ta - RT + q): fields of the prefetched
+        // strip, prefetch of the next strip, filter along y into mid3[q & 1].
+        // The 256-thread shape has the registers to issue the next strip's
+        // loads before filtering; the 512-thread shape (128 VGPRs) loads after.
+        auto y_phase = [&](int q) {
+            if (!yact) return;
+            constexpr bool early = NT == 256;
+            float* dst = &mid3[q & 1][0][0];
+            float fu[YW], fv[YW], fz[YW];
+#pragma unroll
+            for (int k = 0; k < YW; ++k) {
+                fu[k] = pW[k] * pX[k];
+                fv[k] = pF[k] * fu[k];
+                fz[k] = pF[k] * fv[k];
+            }
+            if constexpr (early) load_strip(ta - RT + q + 1);
+#pragma unroll
+            for (int i = 0; i < PY; ++i) {
+                float a0 = gs[0] * fu[i + RS], a1 = gs[0] * fv[i + RS], a2 = gs[0] * fz[i + RS];
+#pragma unroll
+                for (int d = 1; d <= RS; ++d) {
+                    a0 = fmaf(gs[d], fu[i + RS - d] + fu[i + RS + d], a0);
+                    a1 = fmaf(gs[d], fv[i + RS - d] + fv[i + RS + d], a1);
+                    a2 = fmaf(gs[d], fz[i + RS - d] + fz[i + RS + d], a2);
+                }
+                const int o = (yseg * PY + i) * MP + ycol;
+                dst[o] = a0;
+                dst[TY * MP + o] = a1;
+                dst[2 * TY * MP + o] = a2;
+            }
+            if constexpr (!early) load_strip(ta - RT + q + 1);
+        };
+
         // Input frames ta-RT .. tb+RT-1, rounded up to whole ring turns; the
-        // extra steps read frames past the run and store nothing.
+        // extra steps read frames past the run and store nothing.  Interval s
+        // runs the y pass of step s+1 beside the x pass and output of step s,
+        // so one barrier per frame separates the writers of a mid3 buffer from
+        // its readers.
         const int n_in = (tb - ta) + 2 * RT;
         const int n_steps = (n_in + NR - 1) / NR * NR;
         load_strip(ta - RT);
         load_own(ta);
+        y_phase(0);
+        __syncthreads();
 
         for (int s0 = 0; s0 < n_steps; s0 += NR) {
 #pragma unroll
             for (int j = 0; j < NR; ++j) {
                 const int s = s0 + j;
                 const int t_in = ta - RT + s;
-                // ---- Y phase: fields, prefetch of the next strip, filter along y ----
-                // The 256-thread shape has the registers to issue the next
-                // strip's loads before filtering; the 512-thread shape (128
-                // VGPRs) turns the strip into the fields in place and loads
-                // after filtering.
-                if (yact) {
-                    constexpr bool early = NT == 256;
-                    float fu[YW], fv[YW], fz[YW];
-#pragma unroll
-                    for (int k = 0; k < YW; ++k) {
-                        fu[k] = pW[k] * pX[k];
-                        fv[k] = pF[k] * fu[k];
-                        fz[k] = pF[k] * fv[k];
-                    }
-                    if constexpr (early) load_strip(t_in + 1);
-#pragma unroll
-                    for (int i = 0; i < PY; ++i) {
-                        float a0 = gs[0] * fu[i + RS], a1 = gs[0] * fv[i + RS],
-                              a2 = gs[0] * fz[i + RS];
-#pragma unroll
-                        for (int d = 1; d <= RS; ++d) {
-                            a0 = fmaf(gs[d], fu[i + RS - d] + fu[i + RS + d], a0);
-                            a1 = fmaf(gs[d], fv[i + RS - d] + fv[i + RS + d], a1);
-                            a2 = fmaf(gs[d], fz[i + RS - d] + fz[i + RS + d], a2);
-                        }
-                        const int o = (yseg * PY + i) * MP + ycol;
-                        mid3[0][o] = a0;
-                        mid3[1][o] = a1;
-                        mid3[2][o] = a2;
-                    }
-                    if constexpr (!early) load_strip(t_in + 1);
-                }
-                __syncthreads();
-                // ---- X phase: filter along x into ring slot j ----
+                if (s + 1 < n_steps) y_phase(s + 1);
+                // ---- X phase of step s: filter along x into ring slot j ----
+                const float* mid = &mid3[s & 1][0][0];
 #pragma unroll
                 for (int f = 0; f < 3; ++f) {
                     float win[XWA];
-                    const float* src = &mid3[f][orow * MP + ocol];
+                    const float* src = mid + f * TY * MP + orow * MP + ocol;
                     if constexpr (PX % 4 == 0) {
 #pragma unroll
                         for (int q = 0; q < XWA / 4; ++q) {
@@ -500,7 +508,7 @@ __global__ __launch_bounds__(SH::NT, SH::MINW) void step_kernel(StepParams p) {
                     Stor<TS>::template bstoren<PX>(ry, ooff, yv);
                     load_own(t_out + 1);
                 }
-                __syncthreads();  // mid3 is free again
+                __syncthreads();  // mid3[s & 1] is free for step s + 2
             }
         }
     }
