@@ -43,7 +43,12 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="full")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["batch"], default="full",
+                    help="full: one 70x480x854 clip; tiny: 8x64x96; batch: 24 ragged clips "
+                         "(frames 20-100, 240x427 / 360x640 / 480x854) in one batched solve, "
+                         "timed against solving them one by one")
+    ap.add_argument("--clips", type=int, default=24, help="clips in the batch workload")
+    ap.add_argument("--autotune", action="store_true", help="autotune the work plan first")
     ap.add_argument("--storage", choices=["f32", "bf16", "f16"], default="f32")
     ap.add_argument("--tol", type=float, default=1e-5)
     ap.add_argument("--max-iters", type=int, default=5000)
@@ -110,6 +115,94 @@ def precision_report(S, St, kw, K, x_lo):
             "oracle_rayleigh_f32": l32, "oracle_rayleigh": llo}
 
 
+def bench_batch(args):
+    """Batched form: all clips iterated to tol by one persistent launch per
+    step, against the same clips solved one after another (plain)."""
+    import torch
+
+    from paper_1907_02731_amd.solver import BatchSolver, Solver
+    from paper_1907_02731_amd.synth import full_clip, ragged_shapes
+
+    T1, H1, W1, r_t, r_s, s_t, s_s, _ = WORKLOADS["full"]
+    shapes = ragged_shapes(args.clips, seed=3)
+    dev = torch.device("cuda:0")
+    clips = [torch.from_numpy(full_clip(3000 + i, T=T, H=H, W=W)).to(dev)
+             for i, (T, H, W) in enumerate(shapes)]
+    torch.cuda.synchronize()
+    N = sum(T * H * W for T, H, W in shapes)
+    kw = dict(r_t=r_t, r_s=r_s, sigma_t=s_t, sigma_s=s_s, alpha=args.alpha, p=args.p,
+              storage=args.storage)
+    max_iters, tol = (args.iters, 0.0) if args.iters > 0 else (args.max_iters, args.tol)
+    bs = BatchSolver(clips, **kw)
+    plan_info = bs.autotune(steps=4) if args.autotune else None
+    if args.shape >= 0 or args.chunks > 0:
+        pl = bs.plan()
+        bs.set_plan(args.shape if args.shape >= 0 else pl["shape"],
+                    args.chunks if args.chunks > 0 else pl["chunks"])
+
+    def batched():
+        r = bs.iterate(max_iters=max_iters, tol=tol)
+        bs.eigvecs()
+        return r
+
+    for _ in range(args.warmup):
+        batched()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = batched()
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / args.steps
+    iters = [r.iters for r in res]
+    vi = sum(T * H * W * k for (T, H, W), k in zip(shapes, iters))
+    tm = bs.timing()
+
+    # plain: one context per clip, solved one after another (contexts made
+    # outside the timed region, as the batch's is)
+    singles = [Solver(S, **kw) for S in clips]
+    for s_ in singles:
+        s_.iterate(max_iters=2, tol=0.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain_iters = []
+    for s_ in singles:
+        r = s_.iterate(max_iters=max_iters, tol=tol)
+        s_.eigvec()
+        plain_iters.append(r.iters)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    for s_ in singles:
+        s_.close()
+    line = {
+        "metric": "voxel-iterations/s (time to converge to 1e-5)",
+        "value": vi / t_batch,
+        "unit": "voxel-iterations/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": t_batch * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": args.storage, "data": "synthetic",
+        "config": {"workload": f"batch: {len(shapes)} clips, {N} voxels, frames 20-100, "
+                               f"resolutions 240x427/360x640/480x854, r_s={r_s}, r_t={r_t}, "
+                               f"sigma_s={s_s}, sigma_t={s_t}, to delta<{args.tol:g}",
+                   "clips": [list(s) for s in shapes]},
+        "plan": bs.plan(), "autotune": plan_info,
+        "iters_per_clip": iters,
+        "time_to_converge_ms": {"batched": t_batch * 1e3, "plain_sequential": t_plain * 1e3,
+                                "speedup": t_plain / t_batch},
+        "plain_iters_per_clip": plain_iters,
+        "batched_avg_launch_us": tm["loop_ms"] * 1e3 / max(tm["launches"], 1),
+        "roofline": {
+            "bound": "hbm", "kernel": "batch_step_kernel (persistent, all clips)",
+            "achieved": BYTES_PER_VOXEL[args.storage] * vi / (tm["loop_ms"] / 1e3) / 1e9,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": BYTES_PER_VOXEL[args.storage] * vi / (tm["loop_ms"] / 1e3) / 1e9 / HBM_PEAK_GBS,
+            "traffic": None,
+        },
+    }
+    bs.close()
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -117,6 +210,9 @@ def main():
               "the multi-GPU sharding is described in the design notes, not built.",
               file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batch":
+        bench_batch(args)
+        return
 
     import torch
 
@@ -134,6 +230,7 @@ def main():
     kw = dict(r_t=r_t, r_s=r_s, sigma_t=s_t, sigma_s=s_s, alpha=args.alpha, p=args.p,
               storage=args.storage)
     sol = Solver(St, **kw)
+    plan_info = sol.autotune(steps=8) if args.autotune else None
     if args.shape >= 0 or args.chunks > 0:
         pl = sol.plan()
         sol.set_plan(args.shape if args.shape >= 0 else pl["shape"],
@@ -186,6 +283,7 @@ def main():
         },
         "iters_per_step": iters,
         "plan": sol.plan(),
+        "autotune": plan_info,
         "converged": bool(last.converged),
         "delta": last.delta,
         "lambda": last.lam,

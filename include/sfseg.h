@@ -163,6 +163,46 @@ int sfseg_get_plan(const sfseg_ctx *ctx, sfseg_plan *out);
  * iterate. */
 int sfseg_set_plan(sfseg_ctx *ctx, int32_t shape, int32_t chunks);
 
+/* Time `steps` steps of every candidate work plan (both block shapes, 1..4
+ * frame runs per tile where the clip allows) from the default start vector,
+ * keep the fastest, and report it in *best (may be NULL).  Works on single
+ * and batch contexts.  Leaves no iterate (call the iterate entry point
+ * again).  Blocks for the whole search. */
+int sfseg_autotune(sfseg_ctx *ctx, int32_t steps, sfseg_plan *best);
+
+/* ---- Batched form: many clips, one persistent launch per step ----------
+ * A batch iterates n clips of uneven size together.  Every step is one launch
+ * of a persistent kernel over all (clip, tile, frame run) work items of the
+ * clips still iterating; each clip keeps its own norm, Rayleigh quotient,
+ * change and convergence flag (Eqs. (4), (8) per clip), and a clip drops out
+ * of later launches once it has converged or used its step budget.  All clips
+ * must share r_t, r_s, sigma_t, sigma_s, alpha, p and storage (T, H, W may
+ * differ).  Batch contexts accept sfseg_get_plan, sfseg_set_plan,
+ * sfseg_autotune, sfseg_last_timing and sfseg_destroy; the single-clip calls
+ * return SFSEG_ERR_STATE on them. */
+
+/* Create a batch from n >= 1 configurations and device float32 volumes
+ * S[i] (T_i x H_i x W_i) and F[i] (F == NULL or F[i] == NULL means F = S).
+ * Blocks until the input check has finished (SFSEG_ERR_NONFINITE as for
+ * sfseg_create); the caller may then free the inputs. */
+int sfseg_batch_create(const sfseg_config *cfgs, int32_t n, const float *const *S,
+                       const float *const *F, void *stream, sfseg_ctx **out);
+
+/* Number of clips of a batch context. */
+int sfseg_batch_size(const sfseg_ctx *ctx, int32_t *n);
+
+/* Power iteration of every clip (x0 == NULL or x0[i] == NULL: start from
+ * S_i), each stopping on its own at delta < tol or after max_iters steps;
+ * res (host, n entries, may be NULL) receives each clip's outcome.  Returns
+ * the first clip error (its message names the clip); the other clips'
+ * results are still filled in. */
+int sfseg_batch_iterate(sfseg_ctx *ctx, const float *const *x0, int32_t max_iters, double tol,
+                        sfseg_result *res);
+
+/* Write each clip's unit-norm iterate into out[i] (device float32, caller
+ * owned).  SFSEG_ERR_STATE before a successful sfseg_batch_iterate. */
+int sfseg_batch_eigvec(sfseg_ctx *ctx, float *const *out);
+
 /* Timings of the last sfseg_power_iterate (see sfseg_timing).  Host only. */
 int sfseg_last_timing(const sfseg_ctx *ctx, sfseg_timing *out);
 

@@ -91,6 +91,18 @@ def lib():
     L.sfseg_get_plan.restype = ctypes.c_int
     L.sfseg_set_plan.argtypes = [P, ctypes.c_int32, ctypes.c_int32]
     L.sfseg_set_plan.restype = ctypes.c_int
+    L.sfseg_autotune.argtypes = [P, ctypes.c_int32, ctypes.POINTER(Plan)]
+    L.sfseg_autotune.restype = ctypes.c_int
+    L.sfseg_batch_create.argtypes = [pcfg, ctypes.c_int32, ctypes.POINTER(P), ctypes.POINTER(P), P,
+                                     ctypes.POINTER(P)]
+    L.sfseg_batch_create.restype = ctypes.c_int
+    L.sfseg_batch_size.argtypes = [P, ctypes.POINTER(ctypes.c_int32)]
+    L.sfseg_batch_size.restype = ctypes.c_int
+    L.sfseg_batch_iterate.argtypes = [P, ctypes.POINTER(P), ctypes.c_int32, ctypes.c_double,
+                                      ctypes.POINTER(Result)]
+    L.sfseg_batch_iterate.restype = ctypes.c_int
+    L.sfseg_batch_eigvec.argtypes = [P, ctypes.POINTER(P)]
+    L.sfseg_batch_eigvec.restype = ctypes.c_int
     L.sfseg_last_timing.argtypes = [P, ctypes.POINTER(Timing)]
     L.sfseg_last_timing.restype = ctypes.c_int
     L.sfseg_destroy.argtypes = [P]

@@ -16,7 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsfseg.so")
-SOURCES = ["step_f32.hip", "step_bf16.hip", "step_f16.hip", "kernels.hip", "api.hip"]
+SOURCES = ["step_f32.hip", "step_bf16.hip", "step_f16.hip", "kernels.hip", "api.hip",
+           "batch.hip"]
 ARCH = os.environ.get("SFSEG_OFFLOAD_ARCH", "gfx950")
 
 

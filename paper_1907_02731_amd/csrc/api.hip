@@ -18,10 +18,13 @@
 #include "sfseg.h"
 #include "sfseg_internal.h"
 
+#include "host_internal.h"
+
 using sfseg::DevState;
 using sfseg::StepParams;
+using namespace sfseg_host;
 
-namespace {
+namespace sfseg_host {
 
 thread_local char g_err[512] = "";
 
@@ -33,54 +36,9 @@ int fail(int code, const char* fmt, ...) {
     return code;
 }
 
-#define HIP_TRY(expr)                                                                 \
-    do {                                                                              \
-        hipError_t e_ = (expr);                                                       \
-        if (e_ != hipSuccess)                                                         \
-            return fail(e_ == hipErrorOutOfMemory ? SFSEG_ERR_OOM : SFSEG_ERR_HIP,    \
-                        "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__,     \
-                        __LINE__);                                                    \
-    } while (0)
-
 size_t dtype_size(int dt) { return dt == SFSEG_F32 ? 4 : 2; }
 
-constexpr int kChunk = 16;  // steps per captured graph / per host check
-
-}  // namespace
-
-struct sfseg_ctx {
-    sfseg_config cfg{};
-    int device = 0;
-    hipStream_t stream = nullptr;
-    int64_t n = 0;
-    void* w = nullptr;   // S^p
-    void* f = nullptr;   // F
-    void* s0 = nullptr;  // S (default start vector)
-    void* buf[2] = {nullptr, nullptr};
-    void* apply_in = nullptr;
-    void* apply_out = nullptr;
-    DevState* st = nullptr;        // iteration state
-    DevState* st_apply = nullptr;  // state used by sfseg_apply
-    DevState* h_st = nullptr;      // pinned host copies: [0] final, [1..2] per-chunk
-    int32_t* d_bad = nullptr;
-    int32_t* h_bad = nullptr;
-    double* partials = nullptr;
-    int4* items = nullptr;  // step-kernel work items, one per block
-    size_t items_cap = 0;   // capacity of `items` in entries
-    sfseg::Layout L{};
-    int cus = 0;
-    int shape = 0;          // step-kernel block shape (sfseg::step_threads)
-    int chunks = 1;         // runs of frames per tile
-    int step_grid = 0;
-    int ew_grid = 0;  // grid of the element-wise kernels
-    int partial_slots = 0;
-    StepParams params[2]{};  // step from buf[0] -> buf[1] and from buf[1] -> buf[0]
-    hipGraphExec_t graph = nullptr;  // kChunk steps starting from buf[0]
-    hipEvent_t ev[5]{};
-    bool have_iterate = false;
-    int cur = 0;  // buffer holding the current iterate
-    sfseg_timing timing{};
-};
+}  // namespace sfseg_host
 
 extern "C" {
 
@@ -140,6 +98,7 @@ void sfseg_destroy(sfseg_ctx* ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->batch) destroy_batch(ctx->batch);
     if (ctx->graph) (void)hipGraphExecDestroy(ctx->graph);
     for (auto& e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
@@ -155,7 +114,7 @@ void sfseg_destroy(sfseg_ctx* ctx) {
 
 }  // extern "C"
 
-namespace {
+namespace sfseg_host {
 
 // Gaussian taps of Eq. (1), one axis: exp(-d^2 / (2 sigma^2)), d = 0..r,
 // evaluated in float64 and rounded once to float32.
@@ -333,6 +292,24 @@ double storage_gain(const sfseg_config& c, int64_t n) {
     return sqrt((double)n) / (st * ss * ss);
 }
 
+// Copy the start vector into Y_0 and reset the iteration state: tolerance,
+// step budget and storage gain from the host, the rest from init_kernel.
+// `h_st` is pinned host memory that stays untouched until the stream has
+// passed this point.
+int run_init(hipStream_t stream, const sfseg_config& c, const sfseg::Layout& L, int64_t n,
+             const void* src, int src_is_storage, void* y0, DevState* st, DevState* h_st,
+             double* partials, int grid, int32_t max_iters, double tol) {
+    DevState h{};
+    h.tol = tol;
+    h.max_iters = max_iters;
+    h.gain = storage_gain(c, n);
+    h.delta = INFINITY;
+    *h_st = h;
+    HIP_TRY(hipMemcpyAsync(st, h_st, sizeof(DevState), hipMemcpyHostToDevice, stream));
+    HIP_TRY(sfseg::launch_init(c.storage, src, src_is_storage, y0, L, st, partials, grid, stream));
+    return SFSEG_OK;
+}
+
 int launch_steps(sfseg_ctx* ctx, int first_buf, int count) {
     for (int i = 0; i < count; ++i) {
         const int b = (first_buf + i) & 1;
@@ -362,7 +339,7 @@ int ensure_graph(sfseg_ctx* ctx) {
     return SFSEG_OK;
 }
 
-}  // namespace
+}  // namespace sfseg_host
 
 extern "C" {
 
@@ -392,6 +369,7 @@ int sfseg_create(const sfseg_config* cfg, const float* S, const float* F, void* 
 
 int sfseg_set_features(sfseg_ctx* ctx, const float* S, const float* F) {
     if (!ctx) return fail(SFSEG_ERR_INVALID_ARG, "ctx is NULL");
+    if (ctx->batch) return fail(SFSEG_ERR_STATE, "batch context: use the sfseg_batch_* calls");
     if (!S) return fail(SFSEG_ERR_INVALID_ARG, "S is NULL");
     HIP_TRY(hipSetDevice(ctx->device));
     return run_prep(ctx, S, F);
@@ -400,24 +378,17 @@ int sfseg_set_features(sfseg_ctx* ctx, const float* S, const float* F) {
 int sfseg_power_iterate(sfseg_ctx* ctx, const float* x0, int32_t max_iters, double tol,
                         sfseg_result* res) {
     if (!ctx) return fail(SFSEG_ERR_INVALID_ARG, "ctx is NULL");
+    if (ctx->batch) return fail(SFSEG_ERR_STATE, "batch context: use the sfseg_batch_* calls");
     if (max_iters < 0) return fail(SFSEG_ERR_INVALID_ARG, "max_iters must be >= 0");
     if (isnan(tol)) return fail(SFSEG_ERR_INVALID_ARG, "tol is NaN");
     HIP_TRY(hipSetDevice(ctx->device));
     ctx->have_iterate = false;
 
-    // State set-up: tolerance, step budget and storage gain; init_kernel fills the rest.
-    DevState h{};
-    h.tol = tol;
-    h.max_iters = max_iters;
-    h.gain = storage_gain(ctx->cfg, ctx->n);
-    h.delta = INFINITY;
-    *ctx->h_st = h;
     HIP_TRY(hipEventRecord(ctx->ev[0], ctx->stream));
-    HIP_TRY(hipMemcpyAsync(ctx->st, ctx->h_st, sizeof(DevState), hipMemcpyHostToDevice,
-                           ctx->stream));
-    HIP_TRY(sfseg::launch_init(ctx->cfg.storage, x0 ? (const void*)x0 : ctx->s0, x0 ? 0 : 1,
-                               ctx->buf[0], ctx->L, ctx->st, ctx->partials, ctx->ew_grid,
-                               ctx->stream));
+    int rc0 = run_init(ctx->stream, ctx->cfg, ctx->L, ctx->n, x0 ? (const void*)x0 : ctx->s0,
+                       x0 ? 0 : 1, ctx->buf[0], ctx->st, ctx->h_st, ctx->partials, ctx->ew_grid,
+                       max_iters, tol);
+    if (rc0 != SFSEG_OK) return rc0;
     HIP_TRY(hipEventRecord(ctx->ev[1], ctx->stream));
 
     // Keep up to two chunks in flight: while chunk i runs, chunk i+1 is queued
@@ -481,6 +452,7 @@ int sfseg_power_iterate(sfseg_ctx* ctx, const float* x0, int32_t max_iters, doub
 
 int sfseg_eigvec(sfseg_ctx* ctx, float* out) {
     if (!ctx || !out) return fail(SFSEG_ERR_INVALID_ARG, "ctx or out is NULL");
+    if (ctx->batch) return fail(SFSEG_ERR_STATE, "batch context: use sfseg_batch_eigvec");
     if (!ctx->have_iterate) return fail(SFSEG_ERR_STATE, "no iterate: call sfseg_power_iterate first");
     HIP_TRY(hipSetDevice(ctx->device));
     HIP_TRY(sfseg::launch_eigvec(ctx->cfg.storage, ctx->buf[ctx->cur], ctx->st, out, ctx->L,
@@ -490,6 +462,7 @@ int sfseg_eigvec(sfseg_ctx* ctx, float* out) {
 
 int sfseg_apply(sfseg_ctx* ctx, const float* x, float* y) {
     if (!ctx || !x || !y) return fail(SFSEG_ERR_INVALID_ARG, "ctx, x or y is NULL");
+    if (ctx->batch) return fail(SFSEG_ERR_STATE, "batch context: sfseg_apply works on one clip");
     if (x == (const float*)y) return fail(SFSEG_ERR_INVALID_ARG, "x and y may not alias");
     HIP_TRY(hipSetDevice(ctx->device));
     const size_t bytes = (size_t)ctx->L.total * dtype_size(ctx->cfg.storage);
@@ -526,6 +499,7 @@ int sfseg_apply(sfseg_ctx* ctx, const float* x, float* y) {
 
 int sfseg_get_plan(const sfseg_ctx* ctx, sfseg_plan* out) {
     if (!ctx || !out) return fail(SFSEG_ERR_INVALID_ARG, "ctx or out is NULL");
+    if (ctx->batch) return batch_get_plan(ctx, out);
     out->shape = ctx->shape;
     out->chunks = ctx->chunks;
     out->blocks = ctx->step_grid;
@@ -535,6 +509,7 @@ int sfseg_get_plan(const sfseg_ctx* ctx, sfseg_plan* out) {
 
 int sfseg_set_plan(sfseg_ctx* ctx, int32_t shape, int32_t chunks) {
     if (!ctx) return fail(SFSEG_ERR_INVALID_ARG, "ctx is NULL");
+    if (ctx->batch) return batch_set_plan(ctx, shape, chunks);
     if (shape < 0 || shape >= sfseg::STEP_SHAPES)
         return fail(SFSEG_ERR_INVALID_ARG, "shape must be 0..%d", sfseg::STEP_SHAPES - 1);
     if (chunks < 1 || chunks > max_chunks(ctx->cfg))

@@ -15,6 +15,12 @@ hipError_t launch_step_f16(int shape, int rs, int rt, const StepParams& p, int g
 hipError_t occ_step_f32(int shape, int rs, int rt, int* blocks);
 hipError_t occ_step_bf16(int shape, int rs, int rt, int* blocks);
 hipError_t occ_step_f16(int shape, int rs, int rt, int* blocks);
+hipError_t launch_batch_f32(int shape, int rs, int rt, const BatchParams& p, int grid, hipStream_t s);
+hipError_t launch_batch_bf16(int shape, int rs, int rt, const BatchParams& p, int grid, hipStream_t s);
+hipError_t launch_batch_f16(int shape, int rs, int rt, const BatchParams& p, int grid, hipStream_t s);
+hipError_t occ_batch_f32(int shape, int rs, int rt, int* blocks);
+hipError_t occ_batch_bf16(int shape, int rs, int rt, int* blocks);
+hipError_t occ_batch_f16(int shape, int rs, int rt, int* blocks);
 
 namespace {
 using detail::Stor;
@@ -145,6 +151,31 @@ hipError_t launch_step(int dtype, int shape, int rs, int rt, const StepParams& p
         case SFSEG_F32: return launch_step_f32(shape, rs, rt, p, grid, s);
         case SFSEG_BF16: return launch_step_bf16(shape, rs, rt, p, grid, s);
         case SFSEG_F16: return launch_step_f16(shape, rs, rt, p, grid, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_batch_step(int dtype, int shape, int rs, int rt, const BatchParams& p, int grid,
+                             hipStream_t s) {
+    if (shape < 0 || shape >= STEP_SHAPES || rs < 0 || rs > SFSEG_MAX_RS || rt < 0 ||
+        rt > SFSEG_MAX_RT)
+        return hipErrorInvalidValue;
+    switch (dtype) {
+        case SFSEG_F32: return launch_batch_f32(shape, rs, rt, p, grid, s);
+        case SFSEG_BF16: return launch_batch_bf16(shape, rs, rt, p, grid, s);
+        case SFSEG_F16: return launch_batch_f16(shape, rs, rt, p, grid, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t batch_max_blocks_per_cu(int dtype, int shape, int rs, int rt, int* blocks) {
+    if (shape < 0 || shape >= STEP_SHAPES || rs < 0 || rs > SFSEG_MAX_RS || rt < 0 ||
+        rt > SFSEG_MAX_RT)
+        return hipErrorInvalidValue;
+    switch (dtype) {
+        case SFSEG_F32: return occ_batch_f32(shape, rs, rt, blocks);
+        case SFSEG_BF16: return occ_batch_bf16(shape, rs, rt, blocks);
+        case SFSEG_F16: return occ_batch_f16(shape, rs, rt, blocks);
         default: return hipErrorInvalidValue;
     }
 }

@@ -60,6 +60,31 @@ struct StepParams {
     float alpha;
 };
 
+// One clip of a batch, as the batched step kernel sees it.
+struct BatchClip {
+    const void* buf[2];  // Y_k ping-pong buffers (storage dtype, padded layout)
+    const void* w;
+    const void* f;
+    DevState* st;
+    int64_t frame;
+    int32_t T, Wp, PT, PL;
+    int32_t first_item, n_items;  // the clip's items are items[first_item .. +n_items)
+};
+
+// Arguments of the batched persistent step kernel (passed by value).
+struct BatchParams {
+    const BatchClip* clips;
+    const int4* items;    // {clip, x0 | y0 << 16, t0, t1}
+    double* partials;     // 2 doubles per item
+    uint32_t* queue;      // [0..7] next offset in each XCD's run, [8] blocks that left
+    int32_t qfirst[8];    // first item of each XCD's run
+    int32_t qcount[8];    // items in each XCD's run
+    int32_t parity;       // clips still iterating read buf[parity], write buf[1 - parity]
+    float gs[SFSEG_MAX_RS + 1];
+    float gt[SFSEG_MAX_RT + 1];
+    float alpha;
+};
+
 // Output tile of one block and frame: TILE_X columns x TILE_Y rows.
 constexpr int TILE_X = 64;
 constexpr int TILE_Y = 16;
@@ -71,6 +96,9 @@ constexpr int step_threads(int shape) { return shape == 0 ? 256 : 512; }
 hipError_t launch_step(int dtype, int shape, int rs, int rt, const StepParams& p, int grid,
                        hipStream_t stream);
 hipError_t step_max_blocks_per_cu(int dtype, int shape, int rs, int rt, int* blocks);
+hipError_t launch_batch_step(int dtype, int shape, int rs, int rt, const BatchParams& p, int grid,
+                             hipStream_t stream);
+hipError_t batch_max_blocks_per_cu(int dtype, int shape, int rs, int rt, int* blocks);
 
 // Element-wise kernels between unpadded float32 volumes (the ABI) and padded
 // storage volumes (the library's internal layout).

@@ -1,20 +1,30 @@
-// Step-kernel instantiations for float storage: both block shapes, every (r_s, r_t).
+// Step-kernel instantiations for float storage: both block shapes, every
+// (r_s, r_t), single-clip and batched.
 #include "step_kernel.h"
 
 namespace sfseg {
 
-static const detail::StepTable<float>& table_f32() {
+static const detail::StepFns& fns_f32(int shape, int rs, int rt) {
     static const detail::StepTable<float> table;
-    return table;
+    return table.fns[shape][rs * (SFSEG_MAX_RT + 1) + rt];
 }
 
 hipError_t launch_step_f32(int shape, int rs, int rt, const StepParams& p, int grid,
                            hipStream_t s) {
-    return table_f32().launch[shape][rs * (SFSEG_MAX_RT + 1) + rt](p, grid, s);
+    return fns_f32(shape, rs, rt).launch(p, grid, s);
 }
 
 hipError_t occ_step_f32(int shape, int rs, int rt, int* blocks) {
-    return table_f32().occ[shape][rs * (SFSEG_MAX_RT + 1) + rt](blocks);
+    return fns_f32(shape, rs, rt).occ(blocks);
+}
+
+hipError_t launch_batch_f32(int shape, int rs, int rt, const BatchParams& p, int grid,
+                            hipStream_t s) {
+    return fns_f32(shape, rs, rt).batch(p, grid, s);
+}
+
+hipError_t occ_batch_f32(int shape, int rs, int rt, int* blocks) {
+    return fns_f32(shape, rs, rt).batch_occ(blocks);
 }
 
 }  // namespace sfseg

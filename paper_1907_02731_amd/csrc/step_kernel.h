@@ -304,63 +304,49 @@ using ShapeDeep = Shape<2, 4>;    // 512 threads
 //      register ring of 2 r_t + 1 frames and, once frame t - r_t's neighbours
 //      are in, filters along t, combines with its own x, w, F (loaded from L2,
 //      prefetched), stores and reduces.
-template <typename TS, int RS, int RT, typename SH>
-__global__ __launch_bounds__(SH::NT, SH::MINW) void step_kernel(StepParams p) {
-    constexpr int NT = SH::NT, PX = SH::PX, PY = SH::PY, NSEG = SH::NSEG;
-    constexpr int IW = TX + 2 * RS;        // strips: tile columns plus halo
-    constexpr int NYS = TY / PY;           // strips per column
-    constexpr int NYI = IW * NYS;          // y-pass strips per frame
-    constexpr int YW = PY + 2 * RS;        // rows loaded per strip
-    constexpr int XWA = round4(PX + 2 * RS);  // x-pass window, whole 8/16-byte reads
-    constexpr int MP = TX - PX + XWA + (PX == 2 ? 2 : 0);  // y-filtered row pitch
-    constexpr int NR = 2 * RT + 1;         // frames in the register ring
-    constexpr int ES = (int)sizeof(TS);
+template <int RS, int RT, typename SH>
+struct Geom {
+    static constexpr int NT = SH::NT, PX = SH::PX, PY = SH::PY, NSEG = SH::NSEG;
+    static constexpr int IW = TX + 2 * RS;           // strips: tile columns plus halo
+    static constexpr int NYS = TY / PY;              // strips per column
+    static constexpr int NYI = IW * NYS;             // y-pass strips per frame
+    static constexpr int YW = PY + 2 * RS;           // rows loaded per strip
+    static constexpr int XWA = round4(PX + 2 * RS);  // x-pass window, whole 8/16-byte reads
+    static constexpr int MP = TX - PX + XWA + (PX == 2 ? 2 : 0);  // y-filtered row pitch
+    static constexpr int NR = 2 * RT + 1;            // frames in the register ring
     static_assert(NYI <= NT, "one strip per thread");
     static_assert(TY % PY == 0, "whole strips per tile");
     static_assert(MP % 4 == 0, "aligned rows");
+};
 
-    __shared__ __attribute__((aligned(16))) float mid3[2][3][TY * MP];  // y-filtered fields, double-buffered
-    __shared__ double fin[NT];
-
-    DevState* st = p.st;
-    if (st->done) return;
-
-    const float c = st->c;
-    const float alpha = p.alpha;
-    float gs[RS + 1];
-#pragma unroll
-    for (int d = 0; d <= RS; ++d) gs[d] = p.gs[d];
-    float gt[NR];
-#pragma unroll
-    for (int m = 0; m < NR; ++m) gt[m] = p.gt[m < RT ? RT - m : m - RT] * c;
-
-    const TS* __restrict__ X = (const TS*)p.x;
-    const TS* __restrict__ Wt = (const TS*)p.w;
-    const TS* __restrict__ Fv = (const TS*)p.f;
-    TS* __restrict__ Y = (TS*)p.y;
-    const int T = p.T, Wp = p.Wp;
-    const int64_t frame = p.frame;  // Hp * Wp elements
+// One work item: the 64 x 16 tile at picture origin (tx0, ty0) of one clip,
+// output frames [ta, tb).  Accumulates the item's sum(y^2) and sum(y * Y_k)
+// into syy, syx (per thread).  `mid3` is the block's LDS scratch.
+template <typename TS, int RS, int RT, typename SH>
+__device__ __forceinline__ void run_item(const TS* __restrict__ X, const TS* __restrict__ Wt,
+                                         const TS* __restrict__ Fv, TS* __restrict__ Y, int T,
+                                         int Wp, int PT, int PL, int64_t frame, int tx0, int ty0,
+                                         int ta, int tb, const float (&gs)[RS + 1],
+                                         const float (&gt)[2 * RT + 1], float alpha,
+                                         float (&mid3)[2][3][TY * Geom<RS, RT, SH>::MP],
+                                         double& syy, double& syx) {
+    using G = Geom<RS, RT, SH>;
+    constexpr int NT = G::NT, PX = G::PX, PY = G::PY, NSEG = G::NSEG, IW = G::IW,
+                  NYI = G::NYI, YW = G::YW, XWA = G::XWA, MP = G::MP, NR = G::NR;
+    constexpr int ES = (int)sizeof(TS);
     const uint32_t frame_bytes = (uint32_t)(frame * ES);
     const int row_bytes = Wp * ES;
-
     const int tid = threadIdx.x;
     const int orow = tid / NSEG;         // output row inside the tile
     const int ocol = (tid % NSEG) * PX;  // first output column inside the tile
-
-    const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
-    const int4 item = p.items[lb];  // tile origin (picture coords) and frame range
-    const int tx0 = item.x, ty0 = item.y, ta = item.z, tb = item.w;
-
-    double syy = 0.0, syx = 0.0;
-
-    if (tb > ta) {
+    if (tb <= ta) return;
         // This thread's y-pass strip: region column ycol, rows yseg*PY .. +YW.
         const bool yact = tid < NYI;
         const int ycol = yact ? tid % IW : 0;
         const int yseg = yact ? tid / IW : 0;
         // Padded row of window row 0 is ty0 + yseg*PY (PT = r_s), column tx0 + PL - r_s + ycol.
-        const int yoff = ((ty0 + yseg * PY) * Wp + (tx0 + p.PL - RS + ycol)) * ES;
-        const int ooff = ((ty0 + p.PT + orow) * Wp + (tx0 + p.PL + ocol)) * ES;
+        const int yoff = ((ty0 + yseg * PY) * Wp + (tx0 + PL - RS + ycol)) * ES;
+        const int ooff = ((ty0 + PT + orow) * Wp + (tx0 + PL + ocol)) * ES;
 
         // Frames outside the clip read as zeros: their descriptor has no valid
         // bytes (and points at frame 0, so even an unchecked access stays inside
@@ -513,6 +499,31 @@ __global__ __launch_bounds__(SH::NT, SH::MINW) void step_kernel(StepParams p) {
         }
     }
 
+template <typename TS, int RS, int RT, typename SH>
+__global__ __launch_bounds__(SH::NT, SH::MINW) void step_kernel(StepParams p) {
+    using G = Geom<RS, RT, SH>;
+    constexpr int NT = G::NT, NR = G::NR;
+    __shared__ __attribute__((aligned(16))) float mid3[2][3][TY * G::MP];  // y-filtered fields, double-buffered
+    __shared__ double fin[NT];
+
+    DevState* st = p.st;
+    if (st->done) return;
+
+    const float c = st->c;
+    float gs[RS + 1];
+#pragma unroll
+    for (int d = 0; d <= RS; ++d) gs[d] = p.gs[d];
+    float gt[NR];
+#pragma unroll
+    for (int m = 0; m < NR; ++m) gt[m] = p.gt[m < RT ? RT - m : m - RT] * c;
+
+    const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
+    const int4 item = p.items[lb];  // tile origin (picture coords) and frame range
+    double syy = 0.0, syx = 0.0;
+    run_item<TS, RS, RT, SH>((const TS*)p.x, (const TS*)p.w, (const TS*)p.f, (TS*)p.y, p.T, p.Wp,
+                             p.PT, p.PL, p.frame, item.x, item.y, item.z, item.w, gs, gt, p.alpha,
+                             mid3, syy, syx);
+
     if (block_partials_and_ticket<NT>(syy, syx, p.partials, lb, &st->ticket, (uint32_t)gridDim.x)) {
         const double tyy = fixed_order_sum<NT>(p.partials, gridDim.x, 0, fin);
         const double tyx = fixed_order_sum<NT>(p.partials, gridDim.x, 1, fin);
@@ -521,6 +532,97 @@ __global__ __launch_bounds__(SH::NT, SH::MINW) void step_kernel(StepParams p) {
             __hip_atomic_store(&st->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// Batched persistent step: many clips, one launch
+// ---------------------------------------------------------------------------
+// Work items of all clips that are still iterating are handed out through 8
+// queues, one per XCD: queue x holds a contiguous run of items (neighbouring
+// tiles of one clip, so their halos meet in that XCD's L2).  A block drains
+// the queue of its own XCD first, then takes leftovers from the others.  Each
+// item writes its partial sums to its own slot; the last item of a clip to
+// finish reduces that clip's slots in a fixed order and advances only that
+// clip's state, so a converged clip drops out of the next launch.
+template <typename TS, int RS, int RT, typename SH>
+__global__ __launch_bounds__(SH::NT, SH::MINW) void batch_step_kernel(BatchParams p) {
+    using G = Geom<RS, RT, SH>;
+    constexpr int NT = G::NT, NR = G::NR;
+    __shared__ __attribute__((aligned(16))) float mid3[2][3][TY * G::MP];
+    __shared__ double fin[NT];
+    __shared__ int s_item;
+
+    float gs[RS + 1];
+#pragma unroll
+    for (int d = 0; d <= RS; ++d) gs[d] = p.gs[d];
+    const int home = blockIdx.x & 7;
+    int q = home;  // queue being drained
+    int tried = 0;
+
+    for (;;) {
+        if (threadIdx.x == 0) {
+            int it = -1;
+            while (tried < 8) {
+                const uint32_t k = atomicAdd(&p.queue[q], 1u);
+                if ((int)k < p.qcount[q]) {
+                    it = p.qfirst[q] + (int)k;
+                    break;
+                }
+                q = (q + 1) & 7;
+                ++tried;
+            }
+            s_item = it;
+        }
+        __syncthreads();
+        const int it = s_item;
+        __syncthreads();
+        if (it < 0) break;
+
+        const int4 item = p.items[it];  // clip, x0 | y0 << 16, t0, t1
+        const BatchClip* cl = p.clips + item.x;
+        DevState* st = cl->st;
+        if (st->done) continue;  // converged or stopped: nothing to do for this clip
+
+        const float c = st->c;
+        float gt[NR];
+#pragma unroll
+        for (int m = 0; m < NR; ++m) gt[m] = p.gt[m < RT ? RT - m : m - RT] * c;
+        double syy = 0.0, syx = 0.0;
+        run_item<TS, RS, RT, SH>((const TS*)cl->buf[p.parity], (const TS*)cl->w,
+                                 (const TS*)cl->f, (TS*)cl->buf[1 - p.parity], cl->T, cl->Wp,
+                                 cl->PT, cl->PL, cl->frame, item.y & 0xffff, item.y >> 16, item.z,
+                                 item.w, gs, gt, p.alpha, mid3, syy, syx);
+        if (block_partials_and_ticket<NT>(syy, syx, p.partials, it, &st->ticket,
+                                          (uint32_t)cl->n_items)) {
+            const double* part = p.partials + 2 * cl->first_item;
+            const double tyy = fixed_order_sum<NT>(part, cl->n_items, 0, fin);
+            const double tyx = fixed_order_sum<NT>(part, cl->n_items, 1, fin);
+            if (threadIdx.x == 0) {
+                advance_state(st, tyy, tyx);
+                __hip_atomic_store(&st->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+    }
+    // The last block to leave resets the queues for the next launch.
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(&p.queue[8], 1u) == gridDim.x - 1) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i)
+                __hip_atomic_store(&p.queue[i], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+template <typename TS, int RS, int RT, typename SH>
+hipError_t launch_batch_t(const BatchParams& p, int grid, hipStream_t s) {
+    hipLaunchKernelGGL((batch_step_kernel<TS, RS, RT, SH>), dim3(grid), dim3(SH::NT), 0, s, p);
+    return hipGetLastError();
+}
+template <typename TS, int RS, int RT, typename SH>
+hipError_t occ_batch_t(int* blocks) {
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, batch_step_kernel<TS, RS, RT, SH>,
+                                                        SH::NT, 0);
 }
 
 // Launch / occupancy tables over (shape, r_s, r_t) for one storage type.
@@ -536,27 +638,36 @@ hipError_t occ_step_t(int* blocks) {
 }
 
 using LaunchFn = hipError_t (*)(const StepParams&, int, hipStream_t);
+using BatchFn = hipError_t (*)(const BatchParams&, int, hipStream_t);
 using OccFn = hipError_t (*)(int*);
 constexpr int NSHAPES = 2;  // 0: ShapeWide (256 threads), 1: ShapeDeep (512 threads)
 constexpr int NCOMB = (SFSEG_MAX_RS + 1) * (SFSEG_MAX_RT + 1);
 
+struct StepFns {
+    LaunchFn launch;
+    OccFn occ;
+    BatchFn batch;
+    OccFn batch_occ;
+};
+
 template <typename TS, typename SH, int RS, int... RTs>
-void fill_rt(LaunchFn* lt, OccFn* ot, std::integer_sequence<int, RTs...>) {
-    ((lt[RS * (SFSEG_MAX_RT + 1) + RTs] = &launch_step_t<TS, RS, RTs, SH>,
-      ot[RS * (SFSEG_MAX_RT + 1) + RTs] = &occ_step_t<TS, RS, RTs, SH>), ...);
+void fill_rt(StepFns* t, std::integer_sequence<int, RTs...>) {
+    ((t[RS * (SFSEG_MAX_RT + 1) + RTs] =
+          StepFns{&launch_step_t<TS, RS, RTs, SH>, &occ_step_t<TS, RS, RTs, SH>,
+                  &launch_batch_t<TS, RS, RTs, SH>, &occ_batch_t<TS, RS, RTs, SH>}),
+     ...);
 }
 template <typename TS, typename SH, int... RSs>
-void fill_rs(LaunchFn* lt, OccFn* ot, std::integer_sequence<int, RSs...>) {
-    (fill_rt<TS, SH, RSs>(lt, ot, std::make_integer_sequence<int, SFSEG_MAX_RT + 1>{}), ...);
+void fill_rs(StepFns* t, std::integer_sequence<int, RSs...>) {
+    (fill_rt<TS, SH, RSs>(t, std::make_integer_sequence<int, SFSEG_MAX_RT + 1>{}), ...);
 }
 
 template <typename TS>
 struct StepTable {
-    LaunchFn launch[NSHAPES][NCOMB];
-    OccFn occ[NSHAPES][NCOMB];
+    StepFns fns[NSHAPES][NCOMB];
     StepTable() {
-        fill_rs<TS, ShapeWide>(launch[0], occ[0], std::make_integer_sequence<int, SFSEG_MAX_RS + 1>{});
-        fill_rs<TS, ShapeDeep>(launch[1], occ[1], std::make_integer_sequence<int, SFSEG_MAX_RS + 1>{});
+        fill_rs<TS, ShapeWide>(fns[0], std::make_integer_sequence<int, SFSEG_MAX_RS + 1>{});
+        fill_rs<TS, ShapeDeep>(fns[1], std::make_integer_sequence<int, SFSEG_MAX_RS + 1>{});
     }
 };
 

@@ -1,15 +1,19 @@
 """PyTorch-facing wrapper of the libsfseg C ABI.
 
-``Solver`` owns one library context for one clip.  It runs on a stream of
-its own (default priority) and orders itself after / before the caller's
-current stream with stream waits, so tensors produced or consumed on the
-caller's stream need no extra synchronisation.
+``Solver`` owns one library context for one clip, ``BatchSolver`` one for a
+batch of clips of uneven size.  Each runs on a stream of its own (default
+priority) and orders itself after / before the caller's current stream with
+stream waits, so tensors produced or consumed on the caller's stream need no
+extra synchronisation.  ``autotune`` picks the fastest work plan and can keep
+it in a JSON cache keyed by the clip shapes, the graph parameters and the GPU.
 """
 from __future__ import annotations
 
 import ctypes
+import json
+import os
 from dataclasses import dataclass
-from typing import Optional
+from typing import List, Optional, Sequence
 
 import torch
 
@@ -152,3 +156,141 @@ class Solver:
                    "sfseg_last_timing")
         return {"total_ms": t.total_ms, "init_ms": t.init_ms, "loop_ms": t.loop_ms,
                 "iters": int(t.iters), "launches": int(t.launches)}
+
+    def autotune(self, steps: int = 8, cache: Optional[str] = None) -> dict:
+        return _autotune(self, steps, cache, [self.shape])
+
+
+def _arch(device) -> str:
+    return torch.cuda.get_device_properties(device).gcnArchName
+
+
+def _autotune(solver, steps: int, cache: Optional[str], shapes) -> dict:
+    """Pick the fastest work plan (timed by the library) and optionally
+    remember it in `cache`, a JSON file of {key: [shape, chunks]}."""
+    c = solver.cfg
+    key = json.dumps({"shapes": [list(s) for s in shapes], "r_t": c.r_t, "r_s": c.r_s,
+                      "storage": c.storage, "arch": _arch(solver.device)}, sort_keys=True)
+    table = {}
+    if cache and os.path.exists(cache):
+        with open(cache) as fh:
+            table = json.load(fh)
+    if key in table:
+        solver.set_plan(*table[key])
+        return dict(solver.plan(), cached=True)
+    pl = _lib.Plan()
+    with torch.cuda.device(solver.device):
+        solver.stream.wait_stream(torch.cuda.current_stream())
+        _lib.check(_lib.lib().sfseg_autotune(solver._handle(), int(steps), ctypes.byref(pl)),
+                   "sfseg_autotune")
+    if cache:
+        table[key] = [int(pl.shape), int(pl.chunks)]
+        tmp = cache + ".tmp"
+        with open(tmp, "w") as fh:
+            json.dump(table, fh, indent=1, sort_keys=True)
+        os.replace(tmp, cache)
+    return dict(solver.plan(), cached=False)
+
+
+class BatchSolver:
+    """Power iteration of many clips at once (one persistent launch per step).
+
+    ``S`` is a sequence of float32 CUDA tensors (T_i, H_i, W_i); ``F`` is None
+    or a sequence of the same shapes (None entries mean F = S).  All clips
+    share the graph parameters.
+    """
+
+    def __init__(self, S: Sequence[torch.Tensor], F: Optional[Sequence] = None, *, r_t: int = 1,
+                 r_s: int = 2, sigma_t: float = 1.0, sigma_s: float = 1.0, alpha: float = 1.0,
+                 p: float = 0.2, storage: str = "f32",
+                 stream: Optional[torch.cuda.Stream] = None):
+        L = _lib.lib()
+        n = len(S)
+        if n < 1:
+            raise ValueError("need at least one clip")
+        self.shapes = [tuple(int(v) for v in t.shape) for t in S]
+        self.device = S[0].device
+        cfgs = (_lib.Config * n)()
+        for i, sh in enumerate(self.shapes):
+            if len(sh) != 3:
+                raise ValueError("each clip must be (T, H, W)")
+            cfgs[i] = _lib.make_config(*sh, r_t=r_t, r_s=r_s, sigma_t=sigma_t, sigma_s=sigma_s,
+                                       alpha=alpha, p=p, storage=storage)
+        self.cfg = cfgs[0]
+        self._cfgs = cfgs
+        ps = (ctypes.c_void_p * n)(*[_dev_ptr(t, f"S[{i}]", self.shapes[i]) for i, t in enumerate(S)])
+        pf = None
+        if F is not None:
+            pf = (ctypes.c_void_p * n)(*[_dev_ptr(t, f"F[{i}]", self.shapes[i])
+                                         for i, t in enumerate(F)])
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
+        self._ctx = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            self.stream.wait_stream(torch.cuda.current_stream())
+            _lib.check(L.sfseg_batch_create(cfgs, n, ps, pf, ctypes.c_void_p(self.stream.cuda_stream),
+                                            ctypes.byref(self._ctx)), "sfseg_batch_create")
+
+    def __len__(self):
+        return len(self.shapes)
+
+    def close(self) -> None:
+        if getattr(self, "_ctx", None) is not None and self._ctx.value:
+            with torch.cuda.device(self.device):
+                _lib.lib().sfseg_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _handle(self):
+        if not self._ctx.value:
+            raise RuntimeError("solver is closed")
+        return self._ctx
+
+    def iterate(self, x0: Optional[Sequence] = None, max_iters: int = 100,
+                tol: float = 1e-5) -> List[IterResult]:
+        n = len(self)
+        px = None
+        if x0 is not None:
+            px = (ctypes.c_void_p * n)(*[_dev_ptr(t, f"x0[{i}]", self.shapes[i])
+                                         for i, t in enumerate(x0)])
+        res = (_lib.Result * n)()
+        with torch.cuda.device(self.device):
+            self.stream.wait_stream(torch.cuda.current_stream())
+            st = _lib.lib().sfseg_batch_iterate(self._handle(), px, int(max_iters), float(tol), res)
+        out = [IterResult(int(r.iters), bool(r.converged), float(r.delta), float(r.lam))
+               for r in res]
+        self.last_results = out
+        _lib.check(st, "sfseg_batch_iterate")
+        return out
+
+    def eigvecs(self) -> List[torch.Tensor]:
+        with torch.cuda.device(self.device):
+            with torch.cuda.stream(self.stream):
+                outs = [torch.empty(sh, dtype=torch.float32, device=self.device)
+                        for sh in self.shapes]
+            po = (ctypes.c_void_p * len(outs))(*[t.data_ptr() for t in outs])
+            _lib.check(_lib.lib().sfseg_batch_eigvec(self._handle(), po), "sfseg_batch_eigvec")
+            torch.cuda.current_stream().wait_stream(self.stream)
+        return outs
+
+    def plan(self) -> dict:
+        return Solver.plan(self)
+
+    def set_plan(self, shape: int, chunks: int) -> None:
+        Solver.set_plan(self, shape, chunks)
+
+    def timing(self) -> dict:
+        return Solver.timing(self)
+
+    def autotune(self, steps: int = 4, cache: Optional[str] = None) -> dict:
+        return _autotune(self, steps, cache, self.shapes)

@@ -1,0 +1,149 @@
+"""Batched form: clips of uneven size iterated by one persistent launch per
+step, each with its own convergence test.
+
+Every clip of a batch must follow exactly the trajectory it follows alone
+(same per-voxel arithmetic; only the grouping of the float64 norm sums
+differs), match the FP64 oracle after the same number of steps, and stop at
+its own step count.
+"""
+import json
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import OracleConfig, build_adjacency, power_iteration  # noqa: E402
+from paper_1907_02731_amd import _lib  # noqa: E402
+from paper_1907_02731_amd.solver import BatchSolver, Solver  # noqa: E402
+from paper_1907_02731_amd.synth import make_clip  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+CFG = OracleConfig(r_t=1, r_s=2, sigma_t=1.0, sigma_s=1.0, alpha=1.0, p=0.2)
+KW = dict(r_t=CFG.r_t, r_s=CFG.r_s, sigma_t=CFG.sigma_t, sigma_s=CFG.sigma_s, alpha=CFG.alpha,
+          p=CFG.p)
+SHAPES = [(8, 40, 70), (12, 33, 90), (5, 64, 64), (20, 20, 37), (3, 17, 130)]
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(DEV)
+
+
+@pytest.fixture(scope="module")
+def clips():
+    out = []
+    for i, sh in enumerate(SHAPES):
+        S = make_clip(*sh, seed=500 + i, n_blobs=2, noise_sigma=0.1, motion="drift",
+                      dtype=np.float32)
+        out.append((S, build_adjacency(S.astype(np.float64), None, CFG)))
+    return out
+
+
+def test_batch_trajectories_match_single_and_oracle(clips):
+    K = 30
+    with BatchSolver([_t(S) for S, _ in clips], **KW) as bs:
+        assert len(bs) == len(clips)
+        res = bs.iterate(max_iters=K, tol=0.0)
+        xs = [x.cpu().numpy().astype(np.float64).ravel() for x in bs.eigvecs()]
+    for (S, M), r, x in zip(clips, res, xs):
+        assert r.iters == K
+        with Solver(_t(S), **KW) as sol:
+            r1 = sol.iterate(max_iters=K, tol=0.0)
+            x1 = sol.eigvec().cpu().numpy().astype(np.float64).ravel()
+        ref = power_iteration(lambda v: M @ v, S.astype(np.float64).ravel(), K, 0.0)
+        assert np.linalg.norm(x - x1) <= 1e-6
+        assert abs(r.lam - r1.lam) <= 1e-9 * r1.lam
+        assert np.linalg.norm(x - ref["x"]) <= 1e-5
+
+
+def test_each_clip_stops_on_its_own(clips):
+    tol = 1e-5
+    with BatchSolver([_t(S) for S, _ in clips], **KW) as bs:
+        res = bs.iterate(max_iters=3000, tol=tol)
+        xs = [x.cpu().numpy().astype(np.float64).ravel() for x in bs.eigvecs()]
+        t = bs.timing()
+    counts = [r.iters for r in res]
+    print("iterations per clip:", counts, flush=True)
+    assert all(r.converged and r.delta < tol for r in res)
+    assert t["iters"] == max(counts)
+    for (S, M), r, x in zip(clips, res, xs):
+        ref = power_iteration(lambda v: M @ v, S.astype(np.float64).ravel(), 3000, tol)
+        assert abs(ref["iters"] - r.iters) <= 1
+        with Solver(_t(S), **KW) as sol:
+            r1 = sol.iterate(max_iters=3000, tol=tol)
+            x1 = sol.eigvec().cpu().numpy().astype(np.float64).ravel()
+        assert abs(r1.iters - r.iters) <= 1
+        if r1.iters == r.iters:
+            assert np.linalg.norm(x - x1) <= 1e-6
+
+
+@pytest.mark.parametrize("shape,chunks", [(0, 1), (1, 1), (0, 2), (1, 2)])
+def test_batch_plans_agree(clips, shape, chunks):
+    K = 20
+    with BatchSolver([_t(S) for S, _ in clips], **KW) as bs:
+        bs.set_plan(shape, chunks)
+        pl = bs.plan()
+        assert (pl["shape"], pl["chunks"]) == (shape, chunks)
+        bs.iterate(max_iters=K, tol=0.0)
+        xs = [x.cpu().numpy().astype(np.float64).ravel() for x in bs.eigvecs()]
+    for (S, M), x in zip(clips, xs):
+        ref = power_iteration(lambda v: M @ v, S.astype(np.float64).ravel(), K, 0.0)
+        assert np.linalg.norm(x - ref["x"]) <= 1e-5
+
+
+def test_batch_start_vectors_and_errors(clips):
+    S0, M0 = clips[0]
+    S1, _ = clips[1]
+    x0 = np.random.Generator(np.random.PCG64(9)).random(S0.shape).astype(np.float32)
+    with BatchSolver([_t(S0), _t(np.zeros(S1.shape, np.float32))], **KW) as bs:
+        with pytest.raises(_lib.SfsegError) as e:
+            bs.iterate([_t(x0), None], max_iters=10, tol=0.0)
+        assert e.value.status == _lib.SFSEG_ERR_ZERO_NORM
+        assert "clip 1" in str(e.value)
+        # the healthy clip still has its result
+        assert bs.last_results[0].iters == 10
+    with BatchSolver([_t(S0)], **KW) as bs:
+        bs.iterate([_t(x0)], max_iters=10, tol=0.0)
+        x = bs.eigvecs()[0].cpu().numpy().astype(np.float64).ravel()
+    ref = power_iteration(lambda v: M0 @ v, x0.astype(np.float64).ravel(), 10, 0.0)
+    assert np.linalg.norm(x - ref["x"]) <= 1e-5
+
+
+def test_batch_rejects_mixed_parameters_and_single_calls(clips):
+    S0, _ = clips[0]
+    with pytest.raises(_lib.SfsegError) as e:
+        # second clip built with a different radius through the raw ABI
+        cfgs = (_lib.Config * 2)(_lib.make_config(*S0.shape, **KW),
+                                 _lib.make_config(*S0.shape, **dict(KW, r_s=3)))
+        a, b = _t(S0), _t(S0)
+        import ctypes
+        ps = (ctypes.c_void_p * 2)(a.data_ptr(), b.data_ptr())
+        out = ctypes.c_void_p()
+        _lib.check(_lib.lib().sfseg_batch_create(cfgs, 2, ps, None, None, ctypes.byref(out)),
+                   "sfseg_batch_create")
+    assert e.value.status == _lib.SFSEG_ERR_INVALID_ARG
+    with BatchSolver([_t(S0)], **KW) as bs:
+        import ctypes
+        res = _lib.Result()
+        assert _lib.lib().sfseg_power_iterate(bs._handle(), None, 5, 0.0, ctypes.byref(res)) == \
+            _lib.SFSEG_ERR_STATE
+
+
+def test_autotune_single_and_batch_with_cache(clips, tmp_path):
+    cache = str(tmp_path / "plans.json")
+    S0, M0 = clips[0]
+    with Solver(_t(S0), **KW) as sol:
+        pl = sol.autotune(steps=4, cache=cache)
+        assert not pl["cached"]
+        sol.iterate(max_iters=15, tol=0.0)
+        x = sol.eigvec().cpu().numpy().astype(np.float64).ravel()
+    ref = power_iteration(lambda v: M0 @ v, S0.astype(np.float64).ravel(), 15, 0.0)
+    assert np.linalg.norm(x - ref["x"]) <= 1e-5
+    with Solver(_t(S0), **KW) as sol:
+        pl2 = sol.autotune(steps=4, cache=cache)
+        assert pl2["cached"] and (pl2["shape"], pl2["chunks"]) == (pl["shape"], pl["chunks"])
+    with BatchSolver([_t(S) for S, _ in clips], **KW) as bs:
+        pb = bs.autotune(steps=3, cache=cache)
+        assert pb["threads"] in (256, 512)
+    assert len(json.load(open(cache))) == 2
