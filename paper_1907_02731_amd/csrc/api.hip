@@ -136,8 +136,9 @@ int run_prep(sfseg_ctx* ctx, const float* S, const float* F) {
 }
 
 // Padded layout for the step kernel: the picture sits at row PT = r_s and
-// column PL = r_s rounded up to a multiple of 4 (16-byte aligned output rows);
-// the frame holds every tile plus its halo.
+// column PL = r_s rounded up to a multiple of 4; rows are PL + tiles + PL
+// wide, so every tile's region (halo rounded out to 16-byte columns) lies
+// inside the frame and starts on a 16-byte boundary.
 sfseg::Layout make_layout(const sfseg_config& c) {
     sfseg::Layout L{};
     L.T = c.T;
@@ -146,9 +147,9 @@ sfseg::Layout make_layout(const sfseg_config& c) {
     L.tiles_x = (c.W + sfseg::TILE_X - 1) / sfseg::TILE_X;
     L.tiles_y = (c.H + sfseg::TILE_Y - 1) / sfseg::TILE_Y;
     L.PT = c.r_s;
-    L.PL = (c.r_s + 3) / 4 * 4;
+    L.PL = (c.r_s + 3) / 4 * 4;  // halo rounded up to 16-byte columns
     L.Hp = L.PT + L.tiles_y * sfseg::TILE_Y + c.r_s;
-    L.Wp = (L.PL + L.tiles_x * sfseg::TILE_X + c.r_s + 3) / 4 * 4;
+    L.Wp = L.PL + L.tiles_x * sfseg::TILE_X + L.PL;
     L.frame = (int64_t)L.Hp * L.Wp;
     L.total = L.frame * L.T;
     return L;

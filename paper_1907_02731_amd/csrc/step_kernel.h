@@ -24,13 +24,13 @@
 // then stream the same frames at the same time on the same L2, and the halo
 // each one loads is the neighbour's interior, already cached.
 //
-// Per input frame a block loads the tile plus an r_s halo as column strips
-// (raw buffer loads, prefetched one frame ahead), forms the three fields in
-// registers, filters them along y into LDS and along x back into registers,
-// and pushes the result into a register ring of 2 r_t + 1 frames; once the
-// ring holds frames t - r_t .. t + r_t it filters along t, combines, stores
-// frame t and accumulates sum(y^2) and sum(y * Y_k) in float64 on the stored
-// values.  The
+// Per input frame a block loads the tile plus an r_s halo straight into LDS
+// (16-byte direct-to-LDS buffer loads, one frame ahead), forms the three
+// fields in registers from column strips of it, filters them along y into LDS
+// and along x back into registers, and pushes the result into a register ring
+// of 2 r_t + 1 frames; once the ring holds frames t - r_t .. t + r_t it filters
+// along t, combines, stores frame t and accumulates sum(y^2) and sum(y * Y_k)
+// in float64 on the stored values.  The
 // block's partial sums go to memory; the last block to finish reduces all
 // partials in a fixed order and advances the iteration state (norm, Rayleigh
 // quotient, change, convergence flag), so results are bit-reproducible.
@@ -54,6 +54,14 @@ constexpr int kBufferFlags = 0x00020000;  // raw (untyped) buffer, 32-bit lanes
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t bytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes,
                                              kBufferFlags);
+}
+
+// 16 bytes per lane from a buffer straight into LDS (buffer_load_dwordx4 ...
+// lds): lane i's bytes land at dst + 16 i, dst being the same LDS address in
+// every lane of the wave.  The data never passes through registers.
+__device__ __forceinline__ void load_lds16(__amdgpu_buffer_rsrc_t rsrc, void* dst, int voff) {
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc, (__attribute__((address_space(3))) void*)dst,
+                                             16, voff, 0, 0, 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -304,206 +312,251 @@ using ShapeDeep = Shape<2, 4>;    // 512 threads
 //      register ring of 2 r_t + 1 frames and, once frame t - r_t's neighbours
 //      are in, filters along t, combines with its own x, w, F (loaded from L2,
 //      prefetched), stores and reduces.
-template <int RS, int RT, typename SH>
+template <typename TS, int RS, int RT, typename SH>
 struct Geom {
     static constexpr int NT = SH::NT, PX = SH::PX, PY = SH::PY, NSEG = SH::NSEG;
-    static constexpr int IW = TX + 2 * RS;           // strips: tile columns plus halo
+    static constexpr int ES = (int)sizeof(TS);
+    static constexpr int RSA = round4(RS);           // halo rounded to 16-byte columns
+    static constexpr int IW = TX + 2 * RS;           // y-pass strips: tile columns plus halo
+    static constexpr int IH = TY + 2 * RS;           // raw region rows
+    static constexpr int IWA = TX + 2 * RSA;         // raw region columns (16-byte aligned)
+    static constexpr int CPR = IWA * ES / 16;        // 16-byte chunks per region row
+    static constexpr int NCH = IH * CPR;             // chunks per region (one array)
+    static constexpr int NDMA = (NCH + NT - 1) / NT; // direct-to-LDS rounds per array
+    static constexpr int RAWE = IH * IWA;            // elements per region (one array)
     static constexpr int NYS = TY / PY;              // strips per column
     static constexpr int NYI = IW * NYS;             // y-pass strips per frame
-    static constexpr int YW = PY + 2 * RS;           // rows loaded per strip
+    static constexpr int YW = PY + 2 * RS;           // rows per strip
     static constexpr int XWA = round4(PX + 2 * RS);  // x-pass window, whole 8/16-byte reads
     static constexpr int MP = TX - PX + XWA + (PX == 2 ? 2 : 0);  // y-filtered row pitch
     static constexpr int NR = 2 * RT + 1;            // frames in the register ring
     static_assert(NYI <= NT, "one strip per thread");
     static_assert(TY % PY == 0, "whole strips per tile");
     static_assert(MP % 4 == 0, "aligned rows");
+    static_assert((IWA * ES) % 16 == 0, "whole 16-byte chunks per row");
+};
+
+// LDS of one block: the raw x, w, F of the tile plus halo for two frames
+// (filled by direct-to-LDS loads, one frame ahead) and the y-filtered fields.
+template <typename TS, int RS, int RT, typename SH>
+struct StepLds {
+    using G = Geom<TS, RS, RT, SH>;
+    TS raw[2][3][G::RAWE] __attribute__((aligned(16)));
+    float mid3[3][TY * G::MP] __attribute__((aligned(16)));
 };
 
 // One work item: the 64 x 16 tile at picture origin (tx0, ty0) of one clip,
 // output frames [ta, tb).  Accumulates the item's sum(y^2) and sum(y * Y_k)
-// into syy, syx (per thread).  `mid3` is the block's LDS scratch.
+// into syy, syx (per thread).
+//
+// Per input frame:  wait for this frame's region (loaded one frame ago) and
+// barrier; store the previous frame's outputs; start the next frame's region
+// loads straight into LDS (16 bytes per lane, no registers); Y phase: each
+// column strip reads its x, w, F from LDS, forms u, F u, F^2 u and filters
+// them along y into mid3; barrier; X phase: each thread filters its PX-pixel
+// row segment along x, pushes it into the register ring, and once frames
+// t - r_t .. t + r_t are in filters along t, combines with its own x, w, F and
+// reduces.  Stores are deferred by one frame so that the wait for the region
+// loads never waits for a store that was just issued.
 template <typename TS, int RS, int RT, typename SH>
 __device__ __forceinline__ void run_item(const TS* __restrict__ X, const TS* __restrict__ Wt,
                                          const TS* __restrict__ Fv, TS* __restrict__ Y, int T,
                                          int Wp, int PT, int PL, int64_t frame, int tx0, int ty0,
-                                         int ta, int tb, const float (&gs)[RS + 1],
-                                         const float (&gt)[2 * RT + 1], float alpha,
-                                         float (&mid3)[2][3][TY * Geom<RS, RT, SH>::MP],
-                                         double& syy, double& syx) {
-    using G = Geom<RS, RT, SH>;
-    constexpr int NT = G::NT, PX = G::PX, PY = G::PY, NSEG = G::NSEG, IW = G::IW,
-                  NYI = G::NYI, YW = G::YW, XWA = G::XWA, MP = G::MP, NR = G::NR;
+                                         int ta, int tb, const float* gs,
+                                         const float* gt, float alpha,
+                                         StepLds<TS, RS, RT, SH>& lds, double& syy, double& syx) {
+    using G = Geom<TS, RS, RT, SH>;
+    constexpr int NT = G::NT, PX = G::PX, PY = G::PY, NSEG = G::NSEG, NYI = G::NYI,
+                  IW = G::IW, YW = G::YW, XWA = G::XWA, MP = G::MP, NR = G::NR, RSA = G::RSA,
+                  IWA = G::IWA, CPR = G::CPR, NCH = G::NCH, NDMA = G::NDMA, RAWE = G::RAWE;
     constexpr int ES = (int)sizeof(TS);
+    if (tb <= ta) return;
     const uint32_t frame_bytes = (uint32_t)(frame * ES);
-    const int row_bytes = Wp * ES;
     const int tid = threadIdx.x;
+    const int wave = tid >> 6;
     const int orow = tid / NSEG;         // output row inside the tile
     const int ocol = (tid % NSEG) * PX;  // first output column inside the tile
-    if (tb <= ta) return;
-        // This thread's y-pass strip: region column ycol, rows yseg*PY .. +YW.
-        const bool yact = tid < NYI;
-        const int ycol = yact ? tid % IW : 0;
-        const int yseg = yact ? tid / IW : 0;
-        // Padded row of window row 0 is ty0 + yseg*PY (PT = r_s), column tx0 + PL - r_s + ycol.
-        const int yoff = ((ty0 + yseg * PY) * Wp + (tx0 + PL - RS + ycol)) * ES;
-        const int ooff = ((ty0 + PT + orow) * Wp + (tx0 + PL + ocol)) * ES;
 
-        // Frames outside the clip read as zeros: their descriptor has no valid
-        // bytes (and points at frame 0, so even an unchecked access stays inside
-        // the volume).
-        auto rsrc = [&](const TS* base, int t) {
-            const bool tin = t >= 0 && t < T;
-            return make_rsrc(base + (tin ? (int64_t)t * frame : 0), tin ? frame_bytes : 0u);
-        };
-        float pX[YW], pW[YW], pF[YW];  // prefetched strip of the next frame
-        float qX[PX], qW[PX], qF[PX];  // prefetched own x, w, F of the next output frame
+    // Direct-to-LDS chunks of this thread: chunk c = r * NT + tid covers
+    // region row c / CPR, 16 bytes at column (c % CPR) * 16 / ES.  The region
+    // starts at padded row ty0 (PT = r_s) and column tx0 + PL - RSA = tx0.
+    int doff[NDMA];
 #pragma unroll
-        for (int k = 0; k < YW; ++k) pX[k] = pW[k] = pF[k] = 0.f;
-        auto load_strip = [&](int t) {
-            const __amdgpu_buffer_rsrc_t rx = rsrc(X, t), rw = rsrc(Wt, t), rf = rsrc(Fv, t);
+    for (int r = 0; r < NDMA; ++r) {
+        const int cidx = r * NT + tid;
+        const int row = cidx / CPR, cq = cidx - (cidx / CPR) * CPR;
+        doff[r] = ((ty0 + row) * Wp + (tx0 + PL - RSA) + cq * (16 / ES)) * ES;
+    }
+    auto rsrc = [&](const TS* base, int t) {
+        const bool tin = t >= 0 && t < T;
+        return make_rsrc(base + (tin ? (int64_t)t * frame : 0), tin ? frame_bytes : 0u);
+    };
+    // Region of frame t into raw[buf]; frames outside the clip are zeros.
+    auto load_region = [&](int t, int buf) {
+        if (t >= 0 && t < T) {
+            const TS* src[3] = {X, Wt, Fv};
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const __amdgpu_buffer_rsrc_t rr = rsrc(src[a], t);
+#pragma unroll
+                for (int r = 0; r < NDMA; ++r) {
+                    if (r * NT + tid < NCH) {
+                        TS* dst = &lds.raw[buf][a][(r * NT + wave * 64) * (16 / ES)];
+                        load_lds16(rr, dst, doff[r]);
+                    }
+                }
+            }
+        } else {
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                for (int e = tid; e < RAWE; e += NT) lds.raw[buf][a][e] = (TS)0.f;
+        }
+    };
+
+    // This thread's y-pass strip: region column ycol + RSA - RS, rows yseg*PY .. +YW.
+    const bool yact = tid < NYI;
+    const int ycol = yact ? tid % IW : 0;
+    const int yseg = yact ? tid / IW : 0;
+    const int ybase = (yseg * PY) * IWA + ycol + (RSA - RS);
+    const int ooff = ((ty0 + PT + orow) * Wp + (tx0 + PL + ocol)) * ES;
+
+    float qX[PX], qW[PX], qF[PX];  // own x, w, F of the output frame
+    auto load_own = [&](int t) {
+        const __amdgpu_buffer_rsrc_t rx = rsrc(X, t), rw = rsrc(Wt, t), rf = rsrc(Fv, t);
+        Stor<TS>::template bloadn<PX>(rx, ooff, qX);
+        Stor<TS>::template bloadn<PX>(rw, ooff, qW);
+        Stor<TS>::template bloadn<PX>(rf, ooff, qF);
+    };
+
+    float ring[NR][3][PX];  // x/y-filtered fields of the last NR frames
+#pragma unroll
+    for (int j = 0; j < NR; ++j)
+#pragma unroll
+        for (int f = 0; f < 3; ++f)
+#pragma unroll
+            for (int i = 0; i < PX; ++i) ring[j][f][i] = 0.f;
+    float yv[PX];          // outputs waiting to be stored
+    int pending_t = -1;    // their frame (-1: none)
+
+    // Input frames ta-RT .. tb+RT-1, rounded up to whole ring turns; the
+    // extra steps read frames past the run and store nothing.
+    const int n_in = (tb - ta) + 2 * RT;
+    const int n_steps = (n_in + NR - 1) / NR * NR;
+    load_region(ta - RT, 0);
+
+    for (int s0 = 0; s0 < n_steps; s0 += NR) {
+#pragma unroll
+        for (int j = 0; j < NR; ++j) {
+            const int s = s0 + j;
+            const int t_in = ta - RT + s;
+            const int cur = s & 1;
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            __syncthreads();  // raw[cur] is complete; mid3 and raw[cur ^ 1] are free
+            if (pending_t >= 0) {
+                const __amdgpu_buffer_rsrc_t ry = make_rsrc(Y + (int64_t)pending_t * frame, frame_bytes);
+                Stor<TS>::template bstoren<PX>(ry, ooff, yv);
+                pending_t = -1;
+            }
+            const int t_out = t_in - RT;
+            const bool emit = t_out >= ta && t_out < tb;
+            if (emit) load_own(t_out);
+            load_region(t_in + 1, cur ^ 1);
+            // ---- Y phase: fields and filter along y ----
             if (yact) {
+                const TS* rx = &lds.raw[cur][0][ybase];
+                const TS* rw = &lds.raw[cur][1][ybase];
+                const TS* rf = &lds.raw[cur][2][ybase];
+                float fu[YW], fv[YW], fz[YW];
 #pragma unroll
                 for (int k = 0; k < YW; ++k) {
-                    pX[k] = Stor<TS>::bload_s(rx, yoff, k * row_bytes);
-                    pW[k] = Stor<TS>::bload_s(rw, yoff, k * row_bytes);
-                    pF[k] = Stor<TS>::bload_s(rf, yoff, k * row_bytes);
+                    const float xv = (float)rx[k * IWA], wv = (float)rw[k * IWA],
+                                fvv = (float)rf[k * IWA];
+                    fu[k] = wv * xv;
+                    fv[k] = fvv * fu[k];
+                    fz[k] = fvv * fv[k];
+                }
+#pragma unroll
+                for (int i = 0; i < PY; ++i) {
+                    float a0 = gs[0] * fu[i + RS], a1 = gs[0] * fv[i + RS], a2 = gs[0] * fz[i + RS];
+#pragma unroll
+                    for (int d = 1; d <= RS; ++d) {
+                        a0 = fmaf(gs[d], fu[i + RS - d] + fu[i + RS + d], a0);
+                        a1 = fmaf(gs[d], fv[i + RS - d] + fv[i + RS + d], a1);
+                        a2 = fmaf(gs[d], fz[i + RS - d] + fz[i + RS + d], a2);
+                    }
+                    const int o = (yseg * PY + i) * MP + ycol;
+                    lds.mid3[0][o] = a0;
+                    lds.mid3[1][o] = a1;
+                    lds.mid3[2][o] = a2;
                 }
             }
-        };
-        auto load_own = [&](int t) {
-            const __amdgpu_buffer_rsrc_t rx = rsrc(X, t), rw = rsrc(Wt, t), rf = rsrc(Fv, t);
-            Stor<TS>::template bloadn<PX>(rx, ooff, qX);
-            Stor<TS>::template bloadn<PX>(rw, ooff, qW);
-            Stor<TS>::template bloadn<PX>(rf, ooff, qF);
-        };
-
-        float ring[NR][3][PX];  // x/y-filtered fields of the last NR frames
+            __syncthreads();  // mid3 is complete
+            // ---- X phase: filter along x into ring slot j ----
 #pragma unroll
-        for (int j = 0; j < NR; ++j)
+            for (int f = 0; f < 3; ++f) {
+                float win[XWA];
+                const float* src = &lds.mid3[f][orow * MP + ocol];
+                if constexpr (PX % 4 == 0) {
 #pragma unroll
-            for (int f = 0; f < 3; ++f)
+                    for (int q = 0; q < XWA / 4; ++q) {
+                        const float4 v4 = reinterpret_cast<const float4*>(src)[q];
+                        win[4 * q + 0] = v4.x;
+                        win[4 * q + 1] = v4.y;
+                        win[4 * q + 2] = v4.z;
+                        win[4 * q + 3] = v4.w;
+                    }
+                } else {
 #pragma unroll
-                for (int i = 0; i < PX; ++i) ring[j][f][i] = 0.f;
-
-        // Y phase of input step q (frame ta - RT + q): fields of the prefetched
-        // strip, prefetch of the next strip, filter along y into mid3[q & 1].
-        // The 256-thread shape has the registers to issue the next strip's
-        // loads before filtering; the 512-thread shape (128 VGPRs) loads after.
-        auto y_phase = [&](int q) {
-            if (!yact) return;
-            constexpr bool early = NT == 256;
-            float* dst = &mid3[q & 1][0][0];
-            float fu[YW], fv[YW], fz[YW];
+                    for (int q = 0; q < XWA / 2; ++q) {
+                        const float2 v2 = reinterpret_cast<const float2*>(src)[q];
+                        win[2 * q + 0] = v2.x;
+                        win[2 * q + 1] = v2.y;
+                    }
+                }
 #pragma unroll
-            for (int k = 0; k < YW; ++k) {
-                fu[k] = pW[k] * pX[k];
-                fv[k] = pF[k] * fu[k];
-                fz[k] = pF[k] * fv[k];
+                for (int i = 0; i < PX; ++i) {
+                    float a = gs[0] * win[i + RS];
+#pragma unroll
+                    for (int d = 1; d <= RS; ++d)
+                        a = fmaf(gs[d], win[i + RS - d] + win[i + RS + d], a);
+                    ring[j][f][i] = a;
+                }
             }
-            if constexpr (early) load_strip(ta - RT + q + 1);
+            // ---- filter along t, combine (Eq. (7)), reduce frame t_out ----
+            if (emit) {
 #pragma unroll
-            for (int i = 0; i < PY; ++i) {
-                float a0 = gs[0] * fu[i + RS], a1 = gs[0] * fv[i + RS], a2 = gs[0] * fz[i + RS];
+                for (int i = 0; i < PX; ++i) {
+                    float A = 0.f, B = 0.f, C = 0.f;
 #pragma unroll
-                for (int d = 1; d <= RS; ++d) {
-                    a0 = fmaf(gs[d], fu[i + RS - d] + fu[i + RS + d], a0);
-                    a1 = fmaf(gs[d], fv[i + RS - d] + fv[i + RS + d], a1);
-                    a2 = fmaf(gs[d], fz[i + RS - d] + fz[i + RS + d], a2);
-                }
-                const int o = (yseg * PY + i) * MP + ycol;
-                dst[o] = a0;
-                dst[TY * MP + o] = a1;
-                dst[2 * TY * MP + o] = a2;
-            }
-            if constexpr (!early) load_strip(ta - RT + q + 1);
-        };
-
-        // Input frames ta-RT .. tb+RT-1, rounded up to whole ring turns; the
-        // extra steps read frames past the run and store nothing.  Interval s
-        // runs the y pass of step s+1 beside the x pass and output of step s,
-        // so one barrier per frame separates the writers of a mid3 buffer from
-        // its readers.
-        const int n_in = (tb - ta) + 2 * RT;
-        const int n_steps = (n_in + NR - 1) / NR * NR;
-        load_strip(ta - RT);
-        load_own(ta);
-        y_phase(0);
-        __syncthreads();
-
-        for (int s0 = 0; s0 < n_steps; s0 += NR) {
-#pragma unroll
-            for (int j = 0; j < NR; ++j) {
-                const int s = s0 + j;
-                const int t_in = ta - RT + s;
-                if (s + 1 < n_steps) y_phase(s + 1);
-                // ---- X phase of step s: filter along x into ring slot j ----
-                const float* mid = &mid3[s & 1][0][0];
-#pragma unroll
-                for (int f = 0; f < 3; ++f) {
-                    float win[XWA];
-                    const float* src = mid + f * TY * MP + orow * MP + ocol;
-                    if constexpr (PX % 4 == 0) {
-#pragma unroll
-                        for (int q = 0; q < XWA / 4; ++q) {
-                            const float4 v4 = reinterpret_cast<const float4*>(src)[q];
-                            win[4 * q + 0] = v4.x;
-                            win[4 * q + 1] = v4.y;
-                            win[4 * q + 2] = v4.z;
-                            win[4 * q + 3] = v4.w;
-                        }
-                    } else {
-#pragma unroll
-                        for (int q = 0; q < XWA / 2; ++q) {
-                            const float2 v2 = reinterpret_cast<const float2*>(src)[q];
-                            win[2 * q + 0] = v2.x;
-                            win[2 * q + 1] = v2.y;
-                        }
+                    for (int m = 0; m < NR; ++m) {
+                        const int slot = (j + 1 + m) % NR;  // constant once unrolled
+                        A = fmaf(gt[m], ring[slot][0][i], A);  // G * u
+                        C = fmaf(gt[m], ring[slot][1][i], C);  // G * (F u)
+                        B = fmaf(gt[m], ring[slot][2][i], B);  // G * (F^2 u)
                     }
-#pragma unroll
-                    for (int i = 0; i < PX; ++i) {
-                        float a = gs[0] * win[i + RS];
-#pragma unroll
-                        for (int d = 1; d <= RS; ++d)
-                            a = fmaf(gs[d], win[i + RS - d] + win[i + RS + d], a);
-                        ring[j][f][i] = a;
-                    }
+                    const float E = fmaf(-alpha, fmaf(qF[i], fmaf(qF[i], A, -2.f * C), B), A);
+                    const float yq = Stor<TS>::rnd(qW[i] * E);
+                    yv[i] = yq;
+                    syy = fma((double)yq, (double)yq, syy);
+                    syx = fma((double)yq, (double)qX[i], syx);
                 }
-                // ---- once frames t-RT..t+RT are in: filter along t, combine
-                //      (Eq. (7)), store frame t = t_in - RT, reduce ----
-                const int t_out = t_in - RT;
-                if (t_out >= ta && t_out < tb) {
-                    float yv[PX];
-#pragma unroll
-                    for (int i = 0; i < PX; ++i) {
-                        float A = 0.f, B = 0.f, C = 0.f;
-#pragma unroll
-                        for (int m = 0; m < NR; ++m) {
-                            const int slot = (j + 1 + m) % NR;  // constant once unrolled
-                            A = fmaf(gt[m], ring[slot][0][i], A);  // G * u
-                            C = fmaf(gt[m], ring[slot][1][i], C);  // G * (F u)
-                            B = fmaf(gt[m], ring[slot][2][i], B);  // G * (F^2 u)
-                        }
-                        const float E = fmaf(-alpha, fmaf(qF[i], fmaf(qF[i], A, -2.f * C), B), A);
-                        const float yq = Stor<TS>::rnd(qW[i] * E);
-                        yv[i] = yq;
-                        syy = fma((double)yq, (double)yq, syy);
-                        syx = fma((double)yq, (double)qX[i], syx);
-                    }
-                    const __amdgpu_buffer_rsrc_t ry =
-                        make_rsrc(Y + (int64_t)t_out * frame, frame_bytes);
-                    Stor<TS>::template bstoren<PX>(ry, ooff, yv);
-                    load_own(t_out + 1);
-                }
-                __syncthreads();  // mid3[s & 1] is free for step s + 2
+                pending_t = t_out;
             }
         }
     }
+    if (pending_t >= 0) {
+        const __amdgpu_buffer_rsrc_t ry = make_rsrc(Y + (int64_t)pending_t * frame, frame_bytes);
+        Stor<TS>::template bstoren<PX>(ry, ooff, yv);
+    }
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();  // the last region loads have landed before LDS is reused
+}
 
 template <typename TS, int RS, int RT, typename SH>
 __global__ __launch_bounds__(SH::NT, SH::MINW) void step_kernel(StepParams p) {
-    using G = Geom<RS, RT, SH>;
+    using G = Geom<TS, RS, RT, SH>;
     constexpr int NT = G::NT, NR = G::NR;
-    __shared__ __attribute__((aligned(16))) float mid3[2][3][TY * G::MP];  // y-filtered fields, double-buffered
+    __shared__ StepLds<TS, RS, RT, SH> lds;
     __shared__ double fin[NT];
 
     DevState* st = p.st;
@@ -522,7 +575,7 @@ __global__ __launch_bounds__(SH::NT, SH::MINW) void step_kernel(StepParams p) {
     double syy = 0.0, syx = 0.0;
     run_item<TS, RS, RT, SH>((const TS*)p.x, (const TS*)p.w, (const TS*)p.f, (TS*)p.y, p.T, p.Wp,
                              p.PT, p.PL, p.frame, item.x, item.y, item.z, item.w, gs, gt, p.alpha,
-                             mid3, syy, syx);
+                             lds, syy, syx);
 
     if (block_partials_and_ticket<NT>(syy, syx, p.partials, lb, &st->ticket, (uint32_t)gridDim.x)) {
         const double tyy = fixed_order_sum<NT>(p.partials, gridDim.x, 0, fin);
@@ -546,9 +599,9 @@ __global__ __launch_bounds__(SH::NT, SH::MINW) void step_kernel(StepParams p) {
 // clip's state, so a converged clip drops out of the next launch.
 template <typename TS, int RS, int RT, typename SH>
 __global__ __launch_bounds__(SH::NT, SH::MINW) void batch_step_kernel(BatchParams p) {
-    using G = Geom<RS, RT, SH>;
+    using G = Geom<TS, RS, RT, SH>;
     constexpr int NT = G::NT, NR = G::NR;
-    __shared__ __attribute__((aligned(16))) float mid3[2][3][TY * G::MP];
+    __shared__ StepLds<TS, RS, RT, SH> lds;
     __shared__ double fin[NT];
     __shared__ int s_item;
 
@@ -591,7 +644,7 @@ __global__ __launch_bounds__(SH::NT, SH::MINW) void batch_step_kernel(BatchParam
         run_item<TS, RS, RT, SH>((const TS*)cl->buf[p.parity], (const TS*)cl->w,
                                  (const TS*)cl->f, (TS*)cl->buf[1 - p.parity], cl->T, cl->Wp,
                                  cl->PT, cl->PL, cl->frame, item.y & 0xffff, item.y >> 16, item.z,
-                                 item.w, gs, gt, p.alpha, mid3, syy, syx);
+                                 item.w, gs, gt, p.alpha, lds, syy, syx);
         if (block_partials_and_ticket<NT>(syy, syx, p.partials, it, &st->ticket,
                                           (uint32_t)cl->n_items)) {
             const double* part = p.partials + 2 * cl->first_item;
