@@ -18,11 +18,11 @@
 // (w = 0 there), so they are stored and summed like any other.
 //
 // Work layout.  A block owns one 64 x 16 pixel tile over a run of frames (one
-// work item).  Items are ordered chunk by chunk and, inside a chunk, tile row
-// by tile row; blocks are dealt to the 8 XCDs round-robin, so the block index
-// is remapped to give each XCD a contiguous run of items: neighbouring tiles
-// then stream the same frames at the same time on the same L2, and the halo
-// each one loads is the neighbour's interior, already cached.
+// work item).  Items are ordered run by run and, inside a run, tile row by
+// tile row; blocks are dealt to the 8 XCDs round-robin, so the block index is
+// remapped to give each XCD a contiguous range of items: neighbouring tiles
+// then stream the same frames at about the same time on the same L2, and the
+// halo each one loads is mostly the neighbour's interior, already cached.
 //
 // Per input frame a block loads the tile plus an r_s halo straight into LDS
 // (16-byte direct-to-LDS buffer loads, one frame ahead), forms the three
@@ -286,94 +286,113 @@ __device__ __forceinline__ int xcd_logical_block(int b, int G) {
 constexpr int TX = TILE_X, TY = TILE_Y;
 constexpr int round4(int v) { return (v + 3) / 4 * 4; }
 
-// Block shapes: PX outputs per thread along x (so TX / PX thread columns and
-// NT = 16 * TX / PX threads), PY rows per y-pass column strip.
-template <int PX_, int PY_>
+// Block shapes: PX outputs per thread along x, so TX / PX thread columns and
+// NT = 16 * TX / PX threads.
+template <int PX_>
 struct Shape {
-    static constexpr int PX = PX_, PY = PY_;
+    static constexpr int PX = PX_;
     static constexpr int NSEG = TX / PX;
     static constexpr int NT = NSEG * TY;
-    // Minimum waves per SIMD (the second launch-bounds argument): 256-thread
-    // blocks at 2 per CU need 2 (<= 256 VGPRs); 512-thread blocks at 2 per CU
-    // need 4 (<= 128 VGPRs).
-    static constexpr int MINW = NT / 128;
+    static constexpr int NWAVES = NT / 64;
 };
-using ShapeWide = Shape<4, 8>;    // 256 threads
-using ShapeDeep = Shape<2, 4>;    // 512 threads
+using ShapeWide = Shape<4>;  // 256 threads
+using ShapeDeep = Shape<2>;  // 512 threads
 
-// Per input frame a block runs two phases, software-pipelined so that the y
-// phase of frame t+1 shares a barrier interval with the x phase of frame t:
-//   Y: each column strip of the tile-plus-halo (64 + 2 r_s columns, 16 / PY
-//      strips per column) loads PY + 2 r_s rows of x, w, F straight from L2
-//      (prefetched one frame ahead), forms the fields u, F u, F^2 u in
-//      registers and filters them along y into LDS;
-//   X: each thread filters a PX-pixel row segment along x (8- or 16-byte LDS
-//      reads that cover the 32 banks without conflicts), pushes it into its
-//      register ring of 2 r_t + 1 frames and, once frame t - r_t's neighbours
-//      are in, filters along t, combines with its own x, w, F (loaded from L2,
-//      prefetched), stores and reduces.
+// Per input frame a block runs two phases separated by a barrier:
+//   Y: the y pass over the tile plus its x halo (64 + 2 r_s columns).  Every
+//      column is cut into NS row segments of PY rows (the last one shifted up
+//      to end at row 16), one segment per lane: waves 0 .. NS-1 take columns
+//      0..63 of segment 0 .. NS-1, wave NS takes the 2 r_s halo columns of
+//      all segments, so every SIMD gets an equal share.  A lane walks the
+//      PY + 2 r_s region rows of its column once, forms u, F u, F^2 u from the
+//      raw x, w, F in LDS and accumulates each into the PY outputs it touches.
+//   X: each thread filters its PX-pixel row segment along x from 16-byte LDS
+//      reads, pushes it into its register ring of 2 r_t + 1 frames and, once
+//      frame t - r_t's neighbours are in, filters along t, combines with its
+//      own x, w, F, rounds to the storage type and reduces.
+// The raw region of the next frame is loaded straight into LDS while the X
+// phase runs: the Y phase is its only reader and has finished.
 template <typename TS, int RS, int RT, typename SH>
 struct Geom {
-    static constexpr int NT = SH::NT, PX = SH::PX, PY = SH::PY, NSEG = SH::NSEG;
+    static constexpr int NT = SH::NT, PX = SH::PX, NSEG = SH::NSEG, NWAVES = SH::NWAVES;
     static constexpr int ES = (int)sizeof(TS);
     static constexpr int RSA = round4(RS);           // halo rounded to 16-byte columns
-    static constexpr int IW = TX + 2 * RS;           // y-pass strips: tile columns plus halo
+    static constexpr int IW = TX + 2 * RS;           // y-pass columns: tile plus halo
     static constexpr int IH = TY + 2 * RS;           // raw region rows
     static constexpr int IWA = TX + 2 * RSA;         // raw region columns (16-byte aligned)
     static constexpr int CPR = IWA * ES / 16;        // 16-byte chunks per region row
     static constexpr int NCH = IH * CPR;             // chunks per region (one array)
     static constexpr int NDMA = (NCH + NT - 1) / NT; // direct-to-LDS rounds per array
     static constexpr int RAWE = IH * IWA;            // elements per region (one array)
-    static constexpr int NYS = TY / PY;              // strips per column
-    static constexpr int NYI = IW * NYS;             // y-pass strips per frame
-    static constexpr int YW = PY + 2 * RS;           // rows per strip
+    static constexpr int EXT = IW - TX;              // halo columns (taken by wave NS)
+    static constexpr int NS_W = NWAVES - 1;          // segments the waves allow
+    static constexpr int NS_E = EXT > 0 ? 64 / EXT : TY;  // segments the halo wave can hold
+    static constexpr int NS = NS_W < NS_E ? (NS_W < TY ? NS_W : TY) : (NS_E < TY ? NS_E : TY);
+    static constexpr int PY = (TY + NS - 1) / NS;    // rows per segment
+    static constexpr int YW = PY + 2 * RS;           // region rows a segment reads
     static constexpr int XWA = round4(PX + 2 * RS);  // x-pass window, whole 8/16-byte reads
     static constexpr int MP = TX - PX + XWA + (PX == 2 ? 2 : 0);  // y-filtered row pitch
     static constexpr int NR = 2 * RT + 1;            // frames in the register ring
-    static_assert(NYI <= NT, "one strip per thread");
-    static_assert(TY % PY == 0, "whole strips per tile");
+    // The tile's own x, w, F of the last r_t + 1 frames are kept in LDS (taken
+    // from the region while it is there) when that still lets two blocks share
+    // a CU; otherwise the output frame's values are read from memory.
+    static constexpr int RT1 = RT + 1;                // frames in the own-value ring
+    static constexpr int LDS_BASE = 3 * RAWE * ES + 3 * TY * MP * 4;
+    static constexpr bool OWN_LDS = LDS_BASE + RT1 * 3 * TY * TX * ES <= 80 * 1024;
+    // Waves per SIMD the register budget is set for (the second launch-bounds
+    // argument): with the own ring in LDS two blocks share a CU, so two waves
+    // per SIMD (for 256-thread blocks); otherwise three when the register ring
+    // is small enough.
+    static constexpr int RING = NR * 3 * PX;
+    static constexpr int MINW = OWN_LDS ? 2 * NT / 256 : (RING <= 84 ? 3 : 2);
+    static_assert(NS >= 1 && NS * EXT <= 64 && NS + 1 <= NWAVES, "y-pass lane mapping");
+    static_assert(NS * PY >= TY && PY <= TY, "segments cover the tile rows");
     static_assert(MP % 4 == 0, "aligned rows");
     static_assert((IWA * ES) % 16 == 0, "whole 16-byte chunks per row");
 };
 
-// LDS of one block: the raw x, w, F of the tile plus halo for two frames
-// (filled by direct-to-LDS loads, one frame ahead) and the y-filtered fields.
+// LDS of one block: the raw x, w, F of the tile plus halo for one frame
+// (filled by direct-to-LDS loads) and the y-filtered fields.  The raw region
+// doubles as the scratch of the final fixed-order reduction.
 template <typename TS, int RS, int RT, typename SH>
 struct StepLds {
     using G = Geom<TS, RS, RT, SH>;
-    TS raw[2][3][G::RAWE] __attribute__((aligned(16)));
+    union {
+        TS raw[3][G::RAWE];
+        double fin[G::NT];
+    } __attribute__((aligned(16)));
     float mid3[3][TY * G::MP] __attribute__((aligned(16)));
+    TS own[G::OWN_LDS ? G::RT1 : 1][3][G::OWN_LDS ? TY * TX : 4] __attribute__((aligned(16)));
 };
 
 // One work item: the 64 x 16 tile at picture origin (tx0, ty0) of one clip,
 // output frames [ta, tb).  Accumulates the item's sum(y^2) and sum(y * Y_k)
 // into syy, syx (per thread).
 //
-// Per input frame:  wait for this frame's region (loaded one frame ago) and
-// barrier; store the previous frame's outputs; start the next frame's region
-// loads straight into LDS (16 bytes per lane, no registers); Y phase: each
-// column strip reads its x, w, F from LDS, forms u, F u, F^2 u and filters
-// them along y into mid3; barrier; X phase: each thread filters its PX-pixel
-// row segment along x, pushes it into the register ring, and once frames
-// t - r_t .. t + r_t are in filters along t, combines with its own x, w, F and
-// reduces.  Stores are deferred by one frame so that the wait for the region
-// loads never waits for a store that was just issued.
+// Per input frame t:  wait for frame t's region and barrier; store frame
+// t - r_t - 1's outputs (deferred by one frame, so that the wait above never
+// waits for a store just issued); keep the tile's own x, w, F of frame t in
+// the own ring; Y phase; barrier; X phase, with the region loads of frame
+// t + 1 (16 bytes per lane straight into LDS) issued one array per field; t
+// filter, combine with the own x, w, F of frame t - r_t, and reduce.
 template <typename TS, int RS, int RT, typename SH>
 __device__ __forceinline__ void run_item(const TS* __restrict__ X, const TS* __restrict__ Wt,
                                          const TS* __restrict__ Fv, TS* __restrict__ Y, int T,
                                          int Wp, int PT, int PL, int64_t frame, int tx0, int ty0,
-                                         int ta, int tb, const float* gs,
-                                         const float* gt, float alpha,
-                                         StepLds<TS, RS, RT, SH>& lds, double& syy, double& syx) {
+                                         int ta, int tb, const float* gs, const float* gt,
+                                         float alpha, StepLds<TS, RS, RT, SH>& lds, double& syy,
+                                         double& syx) {
     using G = Geom<TS, RS, RT, SH>;
-    constexpr int NT = G::NT, PX = G::PX, PY = G::PY, NSEG = G::NSEG, NYI = G::NYI,
-                  IW = G::IW, YW = G::YW, XWA = G::XWA, MP = G::MP, NR = G::NR, RSA = G::RSA,
-                  IWA = G::IWA, CPR = G::CPR, NCH = G::NCH, NDMA = G::NDMA, RAWE = G::RAWE;
+    constexpr int NT = G::NT, PX = G::PX, NSEG = G::NSEG, IW = G::IW, EXT = G::EXT,
+                  NS = G::NS, PY = G::PY, YW = G::YW, XWA = G::XWA, MP = G::MP, NR = G::NR,
+                  RSA = G::RSA, IWA = G::IWA, CPR = G::CPR, NCH = G::NCH, NDMA = G::NDMA,
+                  RAWE = G::RAWE;
     constexpr int ES = (int)sizeof(TS);
     if (tb <= ta) return;
     const uint32_t frame_bytes = (uint32_t)(frame * ES);
     const int tid = threadIdx.x;
-    const int wave = tid >> 6;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: scalar branches
     const int orow = tid / NSEG;         // output row inside the tile
     const int ocol = (tid % NSEG) * PX;  // first output column inside the tile
 
@@ -391,36 +410,71 @@ __device__ __forceinline__ void run_item(const TS* __restrict__ X, const TS* __r
         const bool tin = t >= 0 && t < T;
         return make_rsrc(base + (tin ? (int64_t)t * frame : 0), tin ? frame_bytes : 0u);
     };
-    // Region of frame t into raw[buf]; frames outside the clip are zeros.
-    auto load_region = [&](int t, int buf) {
+    // Array a (x, w or F) of the region of frame t into raw; frames outside
+    // the clip are zeros.
+    auto load_region_array = [&](int t, int a) {
         if (t >= 0 && t < T) {
-            const TS* src[3] = {X, Wt, Fv};
+            const __amdgpu_buffer_rsrc_t rr = rsrc(a == 0 ? X : (a == 1 ? Wt : Fv), t);
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const __amdgpu_buffer_rsrc_t rr = rsrc(src[a], t);
-#pragma unroll
-                for (int r = 0; r < NDMA; ++r) {
-                    if (r * NT + tid < NCH) {
-                        TS* dst = &lds.raw[buf][a][(r * NT + wave * 64) * (16 / ES)];
-                        load_lds16(rr, dst, doff[r]);
-                    }
-                }
+            for (int r = 0; r < NDMA; ++r) {
+                if (r * NT + tid < NCH)
+                    load_lds16(rr, &lds.raw[a][(r * NT + wave * 64) * (16 / ES)], doff[r]);
             }
         } else {
-#pragma unroll
-            for (int a = 0; a < 3; ++a)
-                for (int e = tid; e < RAWE; e += NT) lds.raw[buf][a][e] = (TS)0.f;
+            for (int e = tid; e < RAWE; e += NT) lds.raw[a][e] = (TS)0.f;
         }
     };
 
-    // This thread's y-pass strip: region column ycol + RSA - RS, rows yseg*PY .. +YW.
-    const bool yact = tid < NYI;
-    const int ycol = yact ? tid % IW : 0;
-    const int yseg = yact ? tid / IW : 0;
-    const int ybase = (yseg * PY) * IWA + ycol + (RSA - RS);
+    // This lane's y-pass column and segment (see Geom).
+    bool yact;
+    int ycol, yseg;
+    if (wave < NS) {
+        yact = true;
+        ycol = lane;
+        yseg = wave;
+    } else {
+        yact = wave == NS && lane < NS * EXT;
+        yseg = yact ? lane / EXT : 0;
+        ycol = yact ? TX + (lane - yseg * EXT) : 0;
+    }
+    const int ys = min(yseg * PY, TY - PY);     // first row of the segment
+    const int yskip = yseg * PY - ys;           // leading rows another segment writes
+    const int ybase = ys * IWA + ycol + (RSA - RS);
     const int ooff = ((ty0 + PT + orow) * Wp + (tx0 + PL + ocol)) * ES;
 
+    // Own x, w, F of this thread's PX pixels: copied from the region into the
+    // own ring while the frame is in LDS (or, without the ring, read from
+    // memory when the frame is emitted).
+    const int rown = (orow + RS) * IWA + RSA + ocol;  // own pixels inside the region
+    const int town = orow * TX + ocol;                // own pixels inside the tile
+    auto save_own = [&](int t) {
+        if constexpr (G::OWN_LDS) {
+            const int slot = t % G::RT1;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                if constexpr (PX * ES == 16) {
+                    *reinterpret_cast<u32x4*>(&lds.own[slot][a][town]) =
+                        *reinterpret_cast<const u32x4*>(&lds.raw[a][rown]);
+                } else if constexpr (PX * ES == 8) {
+                    *reinterpret_cast<u32x2*>(&lds.own[slot][a][town]) =
+                        *reinterpret_cast<const u32x2*>(&lds.raw[a][rown]);
+                } else {
+                    *reinterpret_cast<uint32_t*>(&lds.own[slot][a][town]) =
+                        *reinterpret_cast<const uint32_t*>(&lds.raw[a][rown]);
+                }
+            }
+        }
+    };
     float qX[PX], qW[PX], qF[PX];  // own x, w, F of the output frame
+    auto read_own = [&](int t) {
+        const int slot = t % G::RT1;
+#pragma unroll
+        for (int i = 0; i < PX; ++i) {
+            qX[i] = (float)lds.own[slot][0][town + i];
+            qW[i] = (float)lds.own[slot][1][town + i];
+            qF[i] = (float)lds.own[slot][2][town + i];
+        }
+    };
     auto load_own = [&](int t) {
         const __amdgpu_buffer_rsrc_t rx = rsrc(X, t), rw = rsrc(Wt, t), rf = rsrc(Fv, t);
         Stor<TS>::template bloadn<PX>(rx, ooff, qX);
@@ -442,16 +496,15 @@ __device__ __forceinline__ void run_item(const TS* __restrict__ X, const TS* __r
     // extra steps read frames past the run and store nothing.
     const int n_in = (tb - ta) + 2 * RT;
     const int n_steps = (n_in + NR - 1) / NR * NR;
-    load_region(ta - RT, 0);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) load_region_array(ta - RT, a);
 
     for (int s0 = 0; s0 < n_steps; s0 += NR) {
 #pragma unroll
         for (int j = 0; j < NR; ++j) {
-            const int s = s0 + j;
-            const int t_in = ta - RT + s;
-            const int cur = s & 1;
+            const int t_in = ta - RT + s0 + j;
             asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-            __syncthreads();  // raw[cur] is complete; mid3 and raw[cur ^ 1] are free
+            __syncthreads();  // raw holds frame t_in; mid3 is free
             if (pending_t >= 0) {
                 const __amdgpu_buffer_rsrc_t ry = make_rsrc(Y + (int64_t)pending_t * frame, frame_bytes);
                 Stor<TS>::template bstoren<PX>(ry, ooff, yv);
@@ -459,41 +512,50 @@ __device__ __forceinline__ void run_item(const TS* __restrict__ X, const TS* __r
             }
             const int t_out = t_in - RT;
             const bool emit = t_out >= ta && t_out < tb;
-            if (emit) load_own(t_out);
-            load_region(t_in + 1, cur ^ 1);
-            // ---- Y phase: fields and filter along y ----
+            if (t_in >= ta && t_in < tb) save_own(t_in);
+            // ---- Y phase: fields, filtered along y, into mid3 ----
             if (yact) {
-                const TS* rx = &lds.raw[cur][0][ybase];
-                const TS* rw = &lds.raw[cur][1][ybase];
-                const TS* rf = &lds.raw[cur][2][ybase];
-                float fu[YW], fv[YW], fz[YW];
+                const TS* rx = &lds.raw[0][ybase];
+                const TS* rw = &lds.raw[1][ybase];
+                const TS* rf = &lds.raw[2][ybase];
+                float a0[PY], a1[PY], a2[PY];
+#pragma unroll
+                for (int i = 0; i < PY; ++i) a0[i] = a1[i] = a2[i] = 0.f;
 #pragma unroll
                 for (int k = 0; k < YW; ++k) {
-                    const float xv = (float)rx[k * IWA], wv = (float)rw[k * IWA],
-                                fvv = (float)rf[k * IWA];
-                    fu[k] = wv * xv;
-                    fv[k] = fvv * fu[k];
-                    fz[k] = fvv * fv[k];
+                    const float u = (float)rw[k * IWA] * (float)rx[k * IWA];
+                    const float fv = (float)rf[k * IWA];
+                    const float v = fv * u, z = fv * v;
+#pragma unroll
+                    for (int i = 0; i < PY; ++i) {
+                        const int d = k - i - RS;  // tap offset, constant once unrolled
+                        if (d >= -RS && d <= RS) {
+                            const float g = gs[d < 0 ? -d : d];
+                            a0[i] = fmaf(g, u, a0[i]);
+                            a1[i] = fmaf(g, v, a1[i]);
+                            a2[i] = fmaf(g, z, a2[i]);
+                        }
+                    }
                 }
 #pragma unroll
                 for (int i = 0; i < PY; ++i) {
-                    float a0 = gs[0] * fu[i + RS], a1 = gs[0] * fv[i + RS], a2 = gs[0] * fz[i + RS];
-#pragma unroll
-                    for (int d = 1; d <= RS; ++d) {
-                        a0 = fmaf(gs[d], fu[i + RS - d] + fu[i + RS + d], a0);
-                        a1 = fmaf(gs[d], fv[i + RS - d] + fv[i + RS + d], a1);
-                        a2 = fmaf(gs[d], fz[i + RS - d] + fz[i + RS + d], a2);
+                    if (i >= yskip) {
+                        const int o = (ys + i) * MP + ycol;
+                        lds.mid3[0][o] = a0[i];
+                        lds.mid3[1][o] = a1[i];
+                        lds.mid3[2][o] = a2[i];
                     }
-                    const int o = (yseg * PY + i) * MP + ycol;
-                    lds.mid3[0][o] = a0;
-                    lds.mid3[1][o] = a1;
-                    lds.mid3[2][o] = a2;
                 }
             }
-            __syncthreads();  // mid3 is complete
-            // ---- X phase: filter along x into ring slot j ----
+            __syncthreads();  // mid3 is complete; raw is free
+            if constexpr (!G::OWN_LDS) {
+                if (emit) load_own(t_out);
+            }
+            // ---- X phase: filter along x into ring slot j; the region loads
+            // of frame t_in + 1 are issued one array per field ----
 #pragma unroll
             for (int f = 0; f < 3; ++f) {
+                load_region_array(t_in + 1, f);
                 float win[XWA];
                 const float* src = &lds.mid3[f][orow * MP + ocol];
                 if constexpr (PX % 4 == 0) {
@@ -524,6 +586,7 @@ __device__ __forceinline__ void run_item(const TS* __restrict__ X, const TS* __r
             }
             // ---- filter along t, combine (Eq. (7)), reduce frame t_out ----
             if (emit) {
+                if constexpr (G::OWN_LDS) read_own(t_out);
 #pragma unroll
                 for (int i = 0; i < PX; ++i) {
                     float A = 0.f, B = 0.f, C = 0.f;
@@ -553,11 +616,10 @@ __device__ __forceinline__ void run_item(const TS* __restrict__ X, const TS* __r
 }
 
 template <typename TS, int RS, int RT, typename SH>
-__global__ __launch_bounds__(SH::NT, SH::MINW) void step_kernel(StepParams p) {
+__global__ __launch_bounds__(SH::NT, (Geom<TS, RS, RT, SH>::MINW)) void step_kernel(StepParams p) {
     using G = Geom<TS, RS, RT, SH>;
     constexpr int NT = G::NT, NR = G::NR;
     __shared__ StepLds<TS, RS, RT, SH> lds;
-    __shared__ double fin[NT];
 
     DevState* st = p.st;
     if (st->done) return;
@@ -578,8 +640,8 @@ __global__ __launch_bounds__(SH::NT, SH::MINW) void step_kernel(StepParams p) {
                              lds, syy, syx);
 
     if (block_partials_and_ticket<NT>(syy, syx, p.partials, lb, &st->ticket, (uint32_t)gridDim.x)) {
-        const double tyy = fixed_order_sum<NT>(p.partials, gridDim.x, 0, fin);
-        const double tyx = fixed_order_sum<NT>(p.partials, gridDim.x, 1, fin);
+        const double tyy = fixed_order_sum<NT>(p.partials, gridDim.x, 0, lds.fin);
+        const double tyx = fixed_order_sum<NT>(p.partials, gridDim.x, 1, lds.fin);
         if (threadIdx.x == 0) {
             advance_state(st, tyy, tyx);
             __hip_atomic_store(&st->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -598,11 +660,10 @@ __global__ __launch_bounds__(SH::NT, SH::MINW) void step_kernel(StepParams p) {
 // finish reduces that clip's slots in a fixed order and advances only that
 // clip's state, so a converged clip drops out of the next launch.
 template <typename TS, int RS, int RT, typename SH>
-__global__ __launch_bounds__(SH::NT, SH::MINW) void batch_step_kernel(BatchParams p) {
+__global__ __launch_bounds__(SH::NT, (Geom<TS, RS, RT, SH>::MINW)) void batch_step_kernel(BatchParams p) {
     using G = Geom<TS, RS, RT, SH>;
     constexpr int NT = G::NT, NR = G::NR;
     __shared__ StepLds<TS, RS, RT, SH> lds;
-    __shared__ double fin[NT];
     __shared__ int s_item;
 
     float gs[RS + 1];
@@ -648,8 +709,8 @@ __global__ __launch_bounds__(SH::NT, SH::MINW) void batch_step_kernel(BatchParam
         if (block_partials_and_ticket<NT>(syy, syx, p.partials, it, &st->ticket,
                                           (uint32_t)cl->n_items)) {
             const double* part = p.partials + 2 * cl->first_item;
-            const double tyy = fixed_order_sum<NT>(part, cl->n_items, 0, fin);
-            const double tyx = fixed_order_sum<NT>(part, cl->n_items, 1, fin);
+            const double tyy = fixed_order_sum<NT>(part, cl->n_items, 0, lds.fin);
+            const double tyx = fixed_order_sum<NT>(part, cl->n_items, 1, lds.fin);
             if (threadIdx.x == 0) {
                 advance_state(st, tyy, tyx);
                 __hip_atomic_store(&st->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
