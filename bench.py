@@ -29,6 +29,37 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+# FP32 vector peak without packed-FP32 instructions (the library is built with
+# them disabled): 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA) x 2.4 GHz.
+ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+ALU_PEAK_PACKED_TFLOPS = 157.3  # vendor figure, packed FP32
+
+
+def flops_per_voxel(r_s: int, r_t: int) -> int:
+    """Algorithmic FLOPs of one step per voxel: three fields, each filtered
+    along y, x (2 r_s + 1 taps) and t (2 r_t + 1 taps) at 2 flop per tap;
+    3 to form the fields, 7 for the combine of Eq. (7), 4 for the two float64
+    reduction FMAs."""
+    return 3 * 2 * (2 * (2 * r_s + 1) + (2 * r_t + 1)) + 3 + 7 + 4
+
+
+def roofline(kernel: str, voxels: float, seconds: float, storage: str, r_s: int, r_t: int,
+             traffic):
+    """Roofline entry of the step kernel: bound by VALU arithmetic (packed FP32
+    being unavailable, 176 flop per 16 bytes is above the 9.8 flop/B balance),
+    with the HBM view alongside."""
+    fl = flops_per_voxel(r_s, r_t) * voxels
+    by = BYTES_PER_VOXEL[storage] * voxels
+    tf = fl / seconds / 1e12
+    gbs = by / seconds / 1e9
+    out = {"bound": "alu", "kernel": kernel, "achieved": tf, "peak": ALU_PEAK_TFLOPS,
+           "unit": "TFLOP/s", "frac": tf / ALU_PEAK_TFLOPS, "traffic": traffic,
+           "flops_per_launch": fl, "avg_launch_us": seconds * 1e6,
+           "frac_of_packed_peak": tf / ALU_PEAK_PACKED_TFLOPS,
+           "hbm": {"achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                   "bytes_per_launch": by,
+                   "measured": None if traffic is None else traffic / seconds / 1e9}}
+    return out
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_full_traffic.json")
 KERNEL_SOURCES = ["paper_1907_02731_amd/csrc/step_kernel.h", "paper_1907_02731_amd/csrc/step_f32.hip",
                   "paper_1907_02731_amd/csrc/sfseg_internal.h"]
@@ -220,13 +251,8 @@ def bench_batch(args):
                                 "speedup": t_plain / t_batch},
         "plain_iters_per_clip": plain_iters,
         "batched_avg_launch_us": tm["loop_ms"] * 1e3 / max(tm["launches"], 1),
-        "roofline": {
-            "bound": "hbm", "kernel": "batch_step_kernel (persistent, all clips)",
-            "achieved": BYTES_PER_VOXEL[args.storage] * vi / (tm["loop_ms"] / 1e3) / 1e9,
-            "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": BYTES_PER_VOXEL[args.storage] * vi / (tm["loop_ms"] / 1e3) / 1e9 / HBM_PEAK_GBS,
-            "traffic": None,
-        },
+        "roofline": roofline("batch_step_kernel (persistent, all clips)", vi / max(tm["iters"], 1),
+                             tm["loop_ms"] / 1e3 / max(tm["iters"], 1), args.storage, r_s, r_t, None),
     }
     bs.close()
     print(json.dumps(line), flush=True)
@@ -290,8 +316,6 @@ def main():
     value = N * total_iters / elapsed
     loop_ms = sum(t["loop_ms"] for _, t in recs)
     avg_kernel_s = loop_ms / 1e3 / max(total_iters, 1)
-    bytes_per_launch = BYTES_PER_VOXEL[args.storage] * N
-    achieved = bytes_per_launch / avg_kernel_s / 1e9
     last = recs[-1][0]
 
     line = {
@@ -320,17 +344,8 @@ def main():
         "delta": last.delta,
         "lambda": last.lam,
         "time_to_converge_ms": elapsed * 1e3 / args.steps,
-        "roofline": {
-            "bound": "hbm",
-            "kernel": "step_kernel (fused stencil + reductions)",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(args.workload, args.storage),
-            "avg_launch_us": avg_kernel_s * 1e6,
-            "bytes_per_launch": bytes_per_launch,
-        },
+        "roofline": roofline("step_kernel (fused stencil + reductions)", N, avg_kernel_s,
+                             args.storage, r_s, r_t, measured_traffic(args.workload, args.storage)),
     }
     if args.precision_report:
         line["precision"] = precision_report(S, St, kw, max(iters), out)
