@@ -216,6 +216,73 @@ const char *sfseg_status_string(int status);
 /* Message of the last error raised on the calling thread ("" if none). */
 const char *sfseg_last_error(void);
 
+/* ---- Learned warm start: a small 3D U-Net --------------------------------
+ * Algorithm 1 starts the power iteration from a soft segmentation supplied by
+ * another method.  This network maps the input map S (T x H x W, float32) to
+ * a non-negative estimate x^ of the principal eigenvector; x^ is then passed
+ * as x0 to sfseg_power_iterate, which iterates to the same tolerance as a
+ * cold start, so the method itself decides the result.
+ *
+ * Architecture (fixed): three levels of two 3x3x3 convolutions (zero padding,
+ * bias, ReLU) with widths 16 / 32 / 64; 2x2x2 average pooling over zero-padded
+ * windows (output size ceil(n / 2)); nearest 2x upsampling cropped to the skip
+ * size and concatenated in front of the skip ([up, skip]); a 1x1x1 head and
+ * softplus.  Activations bfloat16, weights float32 masters with bfloat16
+ * copies for the matrix cores, float32 accumulation; loss 1 - cos(x^, target).
+ *
+ * Parameter exchange layout (float32, host): for each layer in the order
+ * enc1a (1->16), enc1b (16->16), enc2a (16->32), enc2b (32->32), bota
+ * (32->64), botb (64->64), dec2a (96->32), dec2b (32->32), dec1a (48->16),
+ * dec1b (16->16), head (16->1, 1x1x1): the weights in row-major (Cout, Cin,
+ * 3, 3, 3) order ((1, 16) for the head), then the Cout biases.
+ *
+ * A network object owns its buffers, sized at creation for volumes up to
+ * max_T x max_H x max_W; all work is ordered on `stream` (NULL: default).
+ * Not thread-safe. */
+typedef struct sfseg_unet sfseg_unet;
+
+/* Number of float32 parameters in the exchange layout. */
+int64_t sfseg_unet_param_count(void);
+
+/* Create a network (weights zero until sfseg_unet_set_params).  training != 0
+ * also allocates gradient buffers.  SFSEG_ERR_INVALID_ARG for sizes < 1 or
+ * max_T * max_H * max_W * 48 >= 2^31; SFSEG_ERR_OOM / SFSEG_ERR_HIP. */
+int sfseg_unet_create(int32_t max_T, int32_t max_H, int32_t max_W, int32_t training, void *stream,
+                      sfseg_unet **out);
+
+/* Copy `count` (= sfseg_unet_param_count()) float32 parameters from / to host
+ * memory.  Setting them resets the Adam moments.  Blocks until done. */
+int sfseg_unet_set_params(sfseg_unet *net, const float *host_params, int64_t count);
+int sfseg_unet_get_params(const sfseg_unet *net, float *host_params, int64_t count);
+
+/* x^ = net(S) for a T x H x W volume (device float32 in and out, caller
+ * owned, contiguous).  Stream-ordered; S is copied, so it may be reused once
+ * the stream reaches this call.  SFSEG_ERR_INVALID_ARG for sizes outside
+ * 1..max. */
+int sfseg_unet_forward(sfseg_unet *net, const float *S, int32_t T, int32_t H, int32_t W,
+                       float *out);
+
+/* Gradients of 1 - cos(x^, target) for the last forward pass (target: device
+ * float32 of the same size), written to the network's gradient buffer;
+ * *loss (host, may be NULL) receives the loss.  Blocks until done.
+ * SFSEG_ERR_STATE without training buffers or forward pass;
+ * SFSEG_ERR_ZERO_NORM if x^ or the target has zero norm. */
+int sfseg_unet_backward(sfseg_unet *net, const float *target, double *loss);
+
+/* Copy the gradients (exchange layout) to host memory.  Blocks. */
+int sfseg_unet_get_grads(const sfseg_unet *net, float *host_grads, int64_t count);
+
+/* One Adam step on the float32 masters with the current gradients (step >= 1
+ * is the bias-correction count), then refresh the bfloat16 copies.  Blocks. */
+int sfseg_unet_adam_step(sfseg_unet *net, double lr, double beta1, double beta2, double eps,
+                         int32_t step);
+
+/* Wait for the network's stream. */
+int sfseg_unet_sync(sfseg_unet *net);
+
+/* Release a network.  NULL-safe; waits for its stream first. */
+void sfseg_unet_destroy(sfseg_unet *net);
+
 #ifdef __cplusplus
 }
 #endif

@@ -111,6 +111,28 @@ def lib():
     L.sfseg_status_string.restype = ctypes.c_char_p
     L.sfseg_last_error.argtypes = []
     L.sfseg_last_error.restype = ctypes.c_char_p
+    i32, i64, dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    pf = ctypes.POINTER(ctypes.c_float)
+    L.sfseg_unet_param_count.argtypes = []
+    L.sfseg_unet_param_count.restype = i64
+    L.sfseg_unet_create.argtypes = [i32, i32, i32, i32, P, ctypes.POINTER(P)]
+    L.sfseg_unet_create.restype = ctypes.c_int
+    L.sfseg_unet_set_params.argtypes = [P, pf, i64]
+    L.sfseg_unet_set_params.restype = ctypes.c_int
+    L.sfseg_unet_get_params.argtypes = [P, pf, i64]
+    L.sfseg_unet_get_params.restype = ctypes.c_int
+    L.sfseg_unet_get_grads.argtypes = [P, pf, i64]
+    L.sfseg_unet_get_grads.restype = ctypes.c_int
+    L.sfseg_unet_forward.argtypes = [P, P, i32, i32, i32, P]
+    L.sfseg_unet_forward.restype = ctypes.c_int
+    L.sfseg_unet_backward.argtypes = [P, P, ctypes.POINTER(dbl)]
+    L.sfseg_unet_backward.restype = ctypes.c_int
+    L.sfseg_unet_adam_step.argtypes = [P, dbl, dbl, dbl, dbl, i32]
+    L.sfseg_unet_adam_step.restype = ctypes.c_int
+    L.sfseg_unet_sync.argtypes = [P]
+    L.sfseg_unet_sync.restype = ctypes.c_int
+    L.sfseg_unet_destroy.argtypes = [P]
+    L.sfseg_unet_destroy.restype = None
     _lib = L
     return L
 

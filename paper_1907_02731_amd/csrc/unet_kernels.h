@@ -1,0 +1,523 @@
+// Kernels of the warm-start network (3D U-Net) for gfx950.
+//
+// The power iteration starts from a soft segmentation (Sec. 4, Algorithm 1);
+// this network maps the input map S to an estimate of the principal
+// eigenvector, and plain iterations then run to the same tolerance.
+//
+// Activations are bfloat16, channels-last: voxel v = (t * H + y) * W + x of a
+// view holds its C channels at base[v * CS + c0 + c] (a view can be a channel
+// slice of a wider buffer, which is how the skip concatenations are formed
+// without copies).  Weights: FP32 master copies in the exchange layout
+// (Cout, Cin, 3, 3, 3); the matrix cores read bfloat16 "fragments" prepared
+// from them.  Accumulation is FP32; loss and bias/head reductions are FP64.
+//
+// Convolutions are implicit GEMMs on v_mfma_f32_16x16x32_bf16:
+//   forward      out[v][co] = b[co] + sum_k A[v][k] Wk[k][co],
+//                k = tap * CIN + ci, A[v][k] = in[v + offset(tap)][ci]
+//                (zero outside the volume), tap = (dt+1)*9 + (dy+1)*3 + (dx+1);
+//   backward-data is the same product with CIN' = COUT, COUT' = CIN and the
+//                taps mirrored (tap' = 26 - tap): it runs the forward kernel
+//                on re-arranged fragments;
+//   weight gradient gW[tap][co][ci] = sum_v gz[v][co] in[v + offset(tap)][ci]
+//                with K = voxels (32 consecutive voxels of a row per step).
+// MFMA operand layout (16x16x32): lane l holds A[i = l % 16][k = 8 (l / 16)
+// + e] and B[k = 8 (l / 16) + e][j = l % 16] for e = 0..7; the result
+// D[i][j] sits in lane j + 16 (i / 4), register i % 4.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+namespace sfseg {
+namespace unet {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+
+// A channels-last bfloat16 view.
+struct View {
+    __bf16* p;
+    int32_t T, H, W;
+    int32_t cs;  // channel stride of a voxel
+    int32_t c0;  // first channel of the view
+};
+
+__device__ __forceinline__ bf16x8 load8(const __bf16* p) {
+    const u32x4_t u = *reinterpret_cast<const u32x4_t*>(p);
+    return __builtin_bit_cast(bf16x8, u);
+}
+
+__device__ __forceinline__ bf16x8 zero8() {
+    const u32x4_t u = {0u, 0u, 0u, 0u};
+    return __builtin_bit_cast(bf16x8, u);
+}
+
+// ---------------------------------------------------------------------------
+// Implicit-GEMM convolution (forward, or backward-data on mirrored fragments)
+// ---------------------------------------------------------------------------
+// A wave computes MT 16-voxel tiles along x of one row (t, y) for all COUT
+// channels.  frag[((q * NB + nb) * 64 + lane)] holds the 8 B-operand values of
+// K chunk q (k = 32 q + 8 (lane / 16) + e) and output block nb (co = 16 nb +
+// lane % 16).  mode 0: + bias, ReLU; mode 1: no bias, multiply by
+// (mask > 0) if mask.p is set.
+constexpr int CONV_MT = 4;
+constexpr int CONV_WAVES = 4;
+
+template <int CIN, int COUT>
+__global__ __launch_bounds__(64 * CONV_WAVES) void conv3_mfma(View in, View out,
+                                                                const bf16x8* __restrict__ frag,
+                                                                const float* __restrict__ bias,
+                                                                View mask, int mode) {
+    constexpr int NB = COUT / 16;
+    constexpr int NQ = (27 * CIN + 31) / 32;
+    static_assert(CIN % 8 == 0 && COUT % 16 == 0, "channel blocking");
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int T = out.T, H = out.H, W = out.W;
+    const int tiles_x = (W + 16 * CONV_MT - 1) / (16 * CONV_MT);
+    const int64_t wt = (int64_t)blockIdx.x * CONV_WAVES + wave;
+    if (wt >= (int64_t)T * H * tiles_x) return;  // whole wave: no barrier follows
+    const int row = (int)(wt / tiles_x);
+    const int x0 = (int)(wt - (int64_t)row * tiles_x) * 16 * CONV_MT;
+    const int t = row / H, y = row - t * H;
+    const int i = lane & 15, g = lane >> 4;
+
+    f32x4 acc[CONV_MT][NB];
+#pragma unroll
+    for (int m = 0; m < CONV_MT; ++m)
+#pragma unroll
+        for (int n = 0; n < NB; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    for (int q = 0; q < NQ; ++q) {
+        const int k = 32 * q + 8 * g;
+        const int tap = k / CIN, c = k - tap * CIN;
+        bf16x8 b[NB];
+#pragma unroll
+        for (int n = 0; n < NB; ++n) b[n] = frag[((int64_t)q * NB + n) * 64 + lane];
+        const int dt = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+        const int ts = t + dt, ys = y + dy;
+        const bool rowok = tap < 27 && ts >= 0 && ts < T && ys >= 0 && ys < H;
+        const int64_t rbase = ((int64_t)ts * H + ys) * W;
+#pragma unroll
+        for (int m = 0; m < CONV_MT; ++m) {
+            const int xs = x0 + 16 * m + i + dx;
+            bf16x8 a = zero8();
+            if (rowok && xs >= 0 && xs < W && x0 + 16 * m + i < W)
+                a = load8(in.p + (rbase + xs) * in.cs + in.c0 + c);
+#pragma unroll
+            for (int n = 0; n < NB; ++n)
+                acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[n], acc[m][n], 0, 0, 0);
+        }
+    }
+    const int64_t obase = ((int64_t)t * H + y) * W;
+#pragma unroll
+    for (int m = 0; m < CONV_MT; ++m) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int xo = x0 + 16 * m + 4 * g + r;
+            if (xo >= W) continue;
+            const int64_t v = obase + xo;
+#pragma unroll
+            for (int n = 0; n < NB; ++n) {
+                const int co = 16 * n + i;
+                float val = acc[m][n][r];
+                if (mode == 0) {
+                    val = fmaxf(val + bias[co], 0.f);
+                } else if (mask.p) {
+                    if (!((float)mask.p[v * mask.cs + mask.c0 + co] > 0.f)) val = 0.f;
+                }
+                out.p[v * out.cs + out.c0 + co] = (__bf16)val;
+            }
+        }
+    }
+}
+
+// First layer: one FP32 input channel, K = the 27 taps (one chunk of 32, the
+// last 5 zero).  Lane group g reads taps 8 g .. 8 g + 7 of its voxel.
+template <int COUT>
+__global__ __launch_bounds__(64 * CONV_WAVES) void conv3_mfma_c1(const float* __restrict__ in,
+                                                                   View out,
+                                                                   const bf16x8* __restrict__ frag,
+                                                                   const float* __restrict__ bias) {
+    constexpr int NB = COUT / 16;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int T = out.T, H = out.H, W = out.W;
+    const int tiles_x = (W + 16 * CONV_MT - 1) / (16 * CONV_MT);
+    const int64_t wt = (int64_t)blockIdx.x * CONV_WAVES + wave;
+    if (wt >= (int64_t)T * H * tiles_x) return;
+    const int row = (int)(wt / tiles_x);
+    const int x0 = (int)(wt - (int64_t)row * tiles_x) * 16 * CONV_MT;
+    const int t = row / H, y = row - t * H;
+    const int i = lane & 15, g = lane >> 4;
+    bf16x8 b[NB];
+#pragma unroll
+    for (int n = 0; n < NB; ++n) b[n] = frag[n * 64 + lane];
+#pragma unroll
+    for (int m = 0; m < CONV_MT; ++m) {
+        const int x = x0 + 16 * m + i;
+        bf16x8 a = zero8();
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int tap = 8 * g + e;
+            const int dt = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+            const int ts = t + dt, ys = y + dy, xs = x + dx;
+            float v = 0.f;
+            if (tap < 27 && x < W && ts >= 0 && ts < T && ys >= 0 && ys < H && xs >= 0 && xs < W)
+                v = in[((int64_t)ts * H + ys) * W + xs];
+            a[e] = (__bf16)v;
+        }
+        f32x4 acc[NB];
+#pragma unroll
+        for (int n = 0; n < NB; ++n)
+            acc[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[n], f32x4{0.f, 0.f, 0.f, 0.f},
+                                                             0, 0, 0);
+        const int64_t obase = ((int64_t)t * H + y) * W;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int xo = x0 + 16 * m + 4 * g + r;
+            if (xo >= W) continue;
+#pragma unroll
+            for (int n = 0; n < NB; ++n) {
+                const int co = 16 * n + i;
+                out.p[(obase + xo) * out.cs + out.c0 + co] = (__bf16)fmaxf(acc[n][r] + bias[co], 0.f);
+            }
+        }
+    }
+}
+
+// B-operand fragments from FP32 weights w[(co * cin + ci) * 27 + tap].
+// mirrored = 0: forward fragments of a (cin -> cout) conv;
+// mirrored = 1: backward-data fragments, i.e. forward fragments of the
+//               (cout -> cin) conv with W'[co' = ci][ci' = co][tap] =
+//               W[co][ci][26 - tap].
+__global__ void make_fragments(const float* __restrict__ w, int cin, int cout, int mirrored,
+                               bf16x8* __restrict__ frag) {
+    const int fin = mirrored ? cout : cin;    // input channels of the product
+    const int fout = mirrored ? cin : cout;   // output channels of the product
+    const int nb_all = fout / 16;
+    const int nq = (27 * fin + 31) / 32;
+    const int total = nq * nb_all * 64;
+    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += gridDim.x * blockDim.x) {
+        const int lane = idx & 63;
+        const int nb = (idx >> 6) % nb_all;
+        const int q = (idx >> 6) / nb_all;
+        bf16x8 v;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int k = 32 * q + 8 * (lane >> 4) + e;
+            const int tap = k / fin, c = k - tap * fin;  // c: input channel of the product
+            const int o = 16 * nb + (lane & 15);         // output channel of the product
+            float x = 0.f;
+            if (tap < 27)
+                x = mirrored ? w[((int64_t)c * cin + o) * 27 + (26 - tap)]
+                             : w[((int64_t)o * cin + c) * 27 + tap];
+            v[e] = (__bf16)x;
+        }
+        frag[idx] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Weight gradient: per (chunk of rows, tap) block partial sums
+// ---------------------------------------------------------------------------
+// gW[tap][co][ci] = sum_v gz[v][co] in[v + offset(tap)][ci].  M = co, N = ci,
+// K = 32 consecutive voxels of a row.  Block (blockIdx.x = chunk, blockIdx.y =
+// tap) covers units [u0, u1) of (row, 32-voxel segment); its four waves split
+// the units, then add their accumulators through LDS in a fixed order.
+// part[((chunk * 27 + tap) * COUT + co) * CIN + ci].
+template <int CIN, int COUT, bool IN_F32>
+__global__ __launch_bounds__(256) void conv3_wgrad(View gz, View in, const float* __restrict__ in32,
+                                                    int units_per_chunk, float* __restrict__ part) {
+    constexpr int MB = COUT / 16;
+    constexpr int NBC = IN_F32 ? 1 : CIN / 16;
+    constexpr int CI = IN_F32 ? 1 : CIN;
+    __shared__ float red[4][MB * NBC * 4 * 64];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int T = gz.T, H = gz.H, W = gz.W;
+    const int segs = (W + 31) / 32;
+    const int64_t units = (int64_t)T * H * segs;
+    const int tap = blockIdx.y;
+    const int dt = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+    const int j = lane & 15, g = lane >> 4;
+    f32x4 acc[MB][NBC];
+#pragma unroll
+    for (int m = 0; m < MB; ++m)
+#pragma unroll
+        for (int n = 0; n < NBC; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int64_t u0 = (int64_t)blockIdx.x * units_per_chunk;
+    int64_t u1 = u0 + units_per_chunk;
+    if (u1 > units) u1 = units;
+    for (int64_t u = u0 + wave; u < u1; u += 4) {
+        const int row = (int)(u / segs);
+        const int xb = (int)(u - (int64_t)row * segs) * 32 + 8 * g;
+        const int t = row / H, y = row - t * H;
+        const int ts = t + dt, ys = y + dy;
+        const bool rowok = ts >= 0 && ts < T && ys >= 0 && ys < H;
+        const int64_t gbase = ((int64_t)t * H + y) * W;
+        const int64_t sbase = ((int64_t)ts * H + ys) * W;
+        bf16x8 a[MB], b[NBC];
+#pragma unroll
+        for (int m = 0; m < MB; ++m) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int x = xb + e;
+                a[m][e] = x < W ? gz.p[(gbase + x) * gz.cs + gz.c0 + 16 * m + j] : (__bf16)0.f;
+            }
+        }
+#pragma unroll
+        for (int n = 0; n < NBC; ++n) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int x = xb + e, xs = x + dx;
+                const bool ok = rowok && x < W && xs >= 0 && xs < W;
+                if constexpr (IN_F32) {
+                    b[n][e] = (ok && j == 0) ? (__bf16)in32[sbase + xs] : (__bf16)0.f;
+                } else {
+                    b[n][e] = ok ? in.p[(sbase + xs) * in.cs + in.c0 + 16 * n + j] : (__bf16)0.f;
+                }
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < MB; ++m)
+#pragma unroll
+            for (int n = 0; n < NBC; ++n)
+                acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], b[n], acc[m][n], 0, 0, 0);
+    }
+#pragma unroll
+    for (int m = 0; m < MB; ++m)
+#pragma unroll
+        for (int n = 0; n < NBC; ++n)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) red[wave][((m * NBC + n) * 4 + r) * 64 + lane] = acc[m][n][r];
+    __syncthreads();
+    float* dst = part + ((int64_t)blockIdx.x * 27 + tap) * COUT * CI;
+    for (int idx = threadIdx.x; idx < MB * NBC * 4 * 64; idx += 256) {
+        const float s = ((red[0][idx] + red[1][idx]) + red[2][idx]) + red[3][idx];
+        const int l = idx & 63, r = (idx >> 6) & 3, mn = idx >> 8;
+        const int m = mn / NBC, n = mn - m * NBC;
+        const int co = 16 * m + 4 * (l >> 4) + r, ci = 16 * n + (l & 15);
+        if (ci < CI) dst[co * CI + ci] = s;
+    }
+}
+
+// gW (exchange layout (co, ci, tap)) = sum over chunks, in chunk order.
+__global__ void wgrad_reduce(const float* __restrict__ part, int chunks, int cin, int cout,
+                             float* __restrict__ gw) {
+    const int n = cout * cin * 27;
+    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += gridDim.x * blockDim.x) {
+        const int tap = idx % 27;
+        const int ci = (idx / 27) % cin;
+        const int co = idx / (27 * cin);
+        double s = 0.0;
+        for (int c = 0; c < chunks; ++c)
+            s += part[(((int64_t)c * 27 + tap) * cout + co) * cin + ci];
+        gw[idx] = (float)s;
+    }
+}
+
+// Per-channel sums of a view over its voxels: block partials (FP64), one row
+// per block, part[block * C + c].
+__global__ void channel_sums(View v, int C, double* __restrict__ part) {
+    extern __shared__ double cs_sm[];
+    const int64_t nvox = (int64_t)v.T * v.H * v.W;
+    const int lanes_per_c = blockDim.x / C;
+    const int c = threadIdx.x % C, sub = threadIdx.x / C;
+    double s = 0.0;
+    if (sub < lanes_per_c) {
+        for (int64_t p = (int64_t)blockIdx.x * lanes_per_c + sub; p < nvox;
+             p += (int64_t)gridDim.x * lanes_per_c)
+            s += (double)(float)v.p[p * v.cs + v.c0 + c];
+    }
+    cs_sm[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x < C) {
+        double tot = 0.0;
+        for (int k = 0; k < lanes_per_c; ++k) tot += cs_sm[k * C + threadIdx.x];
+        part[(int64_t)blockIdx.x * C + threadIdx.x] = tot;
+    }
+}
+
+// out[c] = sum over blocks of part[block * C + c], in block order.
+__global__ void sum_partials(const double* __restrict__ part, int blocks, int C,
+                             float* __restrict__ out) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= C) return;
+    double s = 0.0;
+    for (int b = 0; b < blocks; ++b) s += part[(int64_t)b * C + c];
+    out[c] = (float)s;
+}
+
+// ---------------------------------------------------------------------------
+// Pooling and upsampling
+// ---------------------------------------------------------------------------
+// out (ceil sizes) = 2x2x2 average of in over a zero-padded window.
+__global__ void pool2_fwd(View in, View out, int C) {
+    const int64_t n = (int64_t)out.T * out.H * out.W * C;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(idx % C);
+        const int64_t v = idx / C;
+        const int xo = (int)(v % out.W), yo = (int)((v / out.W) % out.H), to = (int)(v / ((int64_t)out.W * out.H));
+        float s = 0.f;
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b)
+                for (int d = 0; d < 2; ++d) {
+                    const int t = 2 * to + a, y = 2 * yo + b, x = 2 * xo + d;
+                    if (t < in.T && y < in.H && x < in.W)
+                        s += (float)in.p[(((int64_t)t * in.H + y) * in.W + x) * in.cs + in.c0 + c];
+                }
+        out.p[v * out.cs + out.c0 + c] = (__bf16)(s * 0.125f);
+    }
+}
+
+// g_in[v] = g_out[parent(v)] / 8 + skip[v], then zero where act[v] <= 0.
+__global__ void pool2_bwd(View gout, View skip, View act, View gin, int C) {
+    const int64_t n = (int64_t)gin.T * gin.H * gin.W * C;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(idx % C);
+        const int64_t v = idx / C;
+        const int x = (int)(v % gin.W), y = (int)((v / gin.W) % gin.H), t = (int)(v / ((int64_t)gin.W * gin.H));
+        const int64_t pv = ((int64_t)(t >> 1) * gout.H + (y >> 1)) * gout.W + (x >> 1);
+        float s = (float)gout.p[pv * gout.cs + gout.c0 + c] * 0.125f;
+        s += (float)skip.p[v * skip.cs + skip.c0 + c];
+        if (!((float)act.p[v * act.cs + act.c0 + c] > 0.f)) s = 0.f;
+        gin.p[v * gin.cs + gin.c0 + c] = (__bf16)s;
+    }
+}
+
+// out[v] = in[parent(v)] (nearest 2x, cropped to out's size).
+__global__ void up2_fwd(View in, View out, int C) {
+    const int64_t n = (int64_t)out.T * out.H * out.W * C;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(idx % C);
+        const int64_t v = idx / C;
+        const int x = (int)(v % out.W), y = (int)((v / out.W) % out.H), t = (int)(v / ((int64_t)out.W * out.H));
+        const int64_t pv = ((int64_t)(t >> 1) * in.H + (y >> 1)) * in.W + (x >> 1);
+        out.p[v * out.cs + out.c0 + c] = in.p[pv * in.cs + in.c0 + c];
+    }
+}
+
+// g_in[p] = sum of g_out over p's children inside g_out, zero where act[p] <= 0.
+__global__ void up2_bwd(View gout, View act, View gin, int C) {
+    const int64_t n = (int64_t)gin.T * gin.H * gin.W * C;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(idx % C);
+        const int64_t v = idx / C;
+        const int xp = (int)(v % gin.W), yp = (int)((v / gin.W) % gin.H), tp = (int)(v / ((int64_t)gin.W * gin.H));
+        float s = 0.f;
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b)
+                for (int d = 0; d < 2; ++d) {
+                    const int t = 2 * tp + a, y = 2 * yp + b, x = 2 * xp + d;
+                    if (t < gout.T && y < gout.H && x < gout.W)
+                        s += (float)gout.p[(((int64_t)t * gout.H + y) * gout.W + x) * gout.cs + gout.c0 + c];
+                }
+        if (!((float)act.p[v * act.cs + act.c0 + c] > 0.f)) s = 0.f;
+        gin.p[v * gin.cs + gin.c0 + c] = (__bf16)s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Head (1x1x1 conv, softplus), loss and their gradients
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float softplus(float z) { return z > 20.f ? z : log1pf(expf(z)); }
+
+// z[v] = sum_c wh[c] d1[v][c] + bh;  xh[v] = softplus(z[v]).
+__global__ void head_fwd(View d1, const float* __restrict__ wh, float* __restrict__ z,
+                         float* __restrict__ xh) {
+    const int64_t n = (int64_t)d1.T * d1.H * d1.W;
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        float s = wh[16];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) s = fmaf(wh[c], (float)d1.p[v * d1.cs + d1.c0 + c], s);
+        z[v] = s;
+        xh[v] = softplus(s);
+    }
+}
+
+// Block partials (FP64) of sum(xh t), sum(xh^2), sum(t^2): part[3 block + k].
+__global__ void loss_sums(const float* __restrict__ xh, const float* __restrict__ tg, int64_t n,
+                          double* __restrict__ part) {
+    __shared__ double sm[3][256];
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        const double x = xh[v], t = tg[v];
+        a += x * t;
+        b += x * x;
+        c += t * t;
+    }
+    sm[0][threadIdx.x] = a;
+    sm[1][threadIdx.x] = b;
+    sm[2][threadIdx.x] = c;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h)
+            for (int k = 0; k < 3; ++k) sm[k][threadIdx.x] += sm[k][threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x < 3) part[3 * blockIdx.x + threadIdx.x] = sm[threadIdx.x][0];
+}
+
+// Gradient through loss, softplus and head.  coef = (1 / (|xh| |t|), cos / |xh|^2):
+//   dL/dxh = -(t coef0 - xh coef1);  gz = dL/dxh * sigmoid(z);
+//   g_d1[v][c] = gz wh[c] (d1 > 0);  head partials (FP64): sum gz d1[c], sum gz
+//   in hp[block * 17 + c].
+__global__ void head_bwd(View d1, const float* __restrict__ wh, const float* __restrict__ z,
+                         const float* __restrict__ xh, const float* __restrict__ tg, double coef0,
+                         double coef1, View gd1, double* __restrict__ hp) {
+    __shared__ double sm[17][256];
+    double acc[17];
+#pragma unroll
+    for (int c = 0; c < 17; ++c) acc[c] = 0.0;
+    const int64_t n = (int64_t)d1.T * d1.H * d1.W;
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        const float gx = (float)(-(tg[v] * coef0 - xh[v] * coef1));
+        const float gz = gx / (1.f + expf(-z[v]));
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+            const float a = (float)d1.p[v * d1.cs + d1.c0 + c];
+            acc[c] += (double)gz * (double)a;
+            gd1.p[v * gd1.cs + gd1.c0 + c] = (__bf16)(a > 0.f ? gz * wh[c] : 0.f);
+        }
+        acc[16] += (double)gz;
+    }
+#pragma unroll
+    for (int c = 0; c < 17; ++c) sm[c][threadIdx.x] = acc[c];
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h)
+            for (int c = 0; c < 17; ++c) sm[c][threadIdx.x] += sm[c][threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x < 17) hp[17 * blockIdx.x + threadIdx.x] = sm[threadIdx.x][0];
+}
+
+// ---------------------------------------------------------------------------
+// Adam (FP32 master weights)
+// ---------------------------------------------------------------------------
+__global__ void adam_step(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
+                          float* __restrict__ v, int64_t n, float lr, float b1, float b2, float eps,
+                          float c1, float c2) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const float gi = g[i];
+        const float mi = b1 * m[i] + (1.f - b1) * gi;
+        const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    }
+}
+
+}  // namespace unet
+}  // namespace sfseg

@@ -1,0 +1,97 @@
+"""Train the warm-start network and compare warm and cold starts.
+
+    python -m paper_1907_02731_amd.train_warmstart [--n 2000] [--epochs 4] [--out PATH]
+
+1. draws ``n`` seeded synthetic clips of 32 x 128 x 224 (seeds 40000 + i),
+2. computes each clip's principal eigenvector with the plain method (batched
+   power iteration to delta < 1e-6) as the training target,
+3. trains the network with Adam on 1 - cos(x^, x*), one clip per step,
+4. saves the float32 parameters (numpy .npy, exchange layout of sfseg.h),
+5. on held-out full-resolution clips (70 x 480 x 854, seeds 1001 ...) runs the
+   plain method from S (cold) and from the network's estimate (warm) to
+   delta < 1e-5 and prints steps and wall time of both.
+
+Every step of the network and of the power iteration runs in libsfseg's
+kernels; this script only draws the synthetic data and keeps the books.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+from .synth import full_clip
+from .warmstart import (GRAPH, TRAIN_SHAPE, WEIGHTS, UNet, eigenvector_targets, he_init,
+                        save_params, solve_cold, solve_warm, train, training_clips)
+
+
+def log(msg: str) -> None:
+    print(msg, flush=True)
+
+
+def evaluate(net: UNet, seeds, tol: float = 1e-5):
+    rows = []
+    for sd in seeds:
+        S = torch.from_numpy(full_clip(sd)).cuda()
+        solve_cold(S, tol=tol)          # warm caches and kernels once
+        rc, xc, tc = solve_cold(S, tol=tol)
+        rw, xw, tw, ti = solve_warm(S, net, tol=tol)
+        row = {"seed": sd, "cold_steps": rc.iters, "warm_steps": rw.iters,
+               "cold_s": tc, "warm_s": tw, "inference_s": ti,
+               "lambda_rel_diff": abs(rw.lam - rc.lam) / rc.lam,
+               "x_diff": float(torch.linalg.norm(xw - xc))}
+        log(json.dumps(row))
+        rows.append(row)
+        del S
+    return rows
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--n", type=int, default=2000)
+    ap.add_argument("--epochs", type=int, default=4)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--lr-final", type=float, default=5e-5)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--out", default=WEIGHTS)
+    ap.add_argument("--eval-seeds", default="1001,1002")
+    ap.add_argument("--log-every", type=int, default=200)
+    args = ap.parse_args(argv)
+
+    t0 = time.time()
+    clips = []
+    for i in range(0, args.n, 100):
+        clips += training_clips(min(100, args.n - i), seed0=40000 + i)
+        log(f"clips {len(clips)}/{args.n} ({time.time() - t0:.0f}s)")
+    targets = eigenvector_targets(clips, tol=1e-6, log=log)
+    inputs = [torch.from_numpy(c).cuda() for c in clips]
+    del clips
+    log(f"data ready ({time.time() - t0:.0f}s)")
+
+    with UNet(TRAIN_SHAPE, training=True) as net:
+        net.set_params(he_init(args.seed))
+        losses = train(net, inputs, targets, epochs=args.epochs, lr=args.lr,
+                       lr_final=args.lr_final, seed=args.seed, log=log, log_every=args.log_every)
+        params = net.get_params()
+    save_params(params, args.out)
+    log(f"saved {args.out}; final mean loss {np.mean(losses[-200:]):.5f} ({time.time() - t0:.0f}s)")
+    del inputs, targets
+    torch.cuda.empty_cache()
+
+    with UNet((70, 480, 854)) as net:
+        net.set_params(params)
+        rows = evaluate(net, [int(s) for s in args.eval_seeds.split(",") if s])
+    log(json.dumps({"mean_cold_steps": float(np.mean([r["cold_steps"] for r in rows])),
+                    "mean_warm_steps": float(np.mean([r["warm_steps"] for r in rows])),
+                    "mean_cold_s": float(np.mean([r["cold_s"] for r in rows])),
+                    "mean_warm_s": float(np.mean([r["warm_s"] for r in rows]))}))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
