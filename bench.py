@@ -100,7 +100,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["batch"], default="full",
+    ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["batch", "warmstart"], default="full",
                     help="full: one 70x480x854 clip; tiny: 8x64x96; batch: 24 ragged clips "
                          "(frames 20-100, 240x427 / 360x640 / 480x854) in one batched solve, "
                          "timed against solving them one by one")
@@ -258,6 +258,57 @@ def bench_batch(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_warmstart(args):
+    """Learned warm start on the full-resolution clip: network inference, then
+    the plain method from its estimate to the same tolerance, against the plain
+    method from S (cold start); both timed end to end, inputs in HBM."""
+    import torch
+
+    from paper_1907_02731_amd.synth import full_clip
+    from paper_1907_02731_amd.warmstart import (GRAPH, WEIGHTS, UNet, load_params, solve_cold,
+                                                solve_warm)
+
+    if not os.path.exists(WEIGHTS):
+        print(f"bench.py: no trained weights at {WEIGHTS} (train them with "
+              "python -m paper_1907_02731_amd.train_warmstart)", file=sys.stderr)
+        sys.exit(2)
+    T, H, W = 70, 480, 854
+    S = torch.from_numpy(full_clip(1)).cuda()
+    net = UNet((T, H, W))
+    net.set_params(load_params(WEIGHTS))
+    for _ in range(args.warmup):
+        solve_cold(S, tol=args.tol, graph=GRAPH)
+        solve_warm(S, net, tol=args.tol, graph=GRAPH)
+    cold, warm = [], []
+    for _ in range(args.steps):
+        cold.append(solve_cold(S, tol=args.tol, graph=GRAPH))
+        warm.append(solve_warm(S, net, tol=args.tol, graph=GRAPH))
+    net.close()
+    tc = float(np.median([c[2] for c in cold]))
+    tw = float(np.median([w[2] for w in warm]))
+    ti = float(np.median([w[3] for w in warm]))
+    rc, rw = cold[-1][0], warm[-1][0]
+    N = T * H * W
+    line = {
+        "metric": "time to converge to 1e-5, warm start (network + plain iterations) vs cold start",
+        "value": N * rc.iters / tw,
+        "unit": "voxel-iterations/s (cold-start iterations per warm-start second)",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": tw * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32 (network bf16)", "data": "synthetic",
+        "config": {"workload": "warmstart: one 70x480x854 clip (seed 1, held out from training), "
+                               "r_s=5, r_t=2, sigma_s=2.0, sigma_t=1.0, alpha=1.0, p=0.2, tol 1e-5",
+                   "T": T, "H": H, "W": W, "tol": args.tol},
+        "cold": {"steps": rc.iters, "seconds": tc},
+        "warm": {"steps": rw.iters, "seconds": tw, "inference_seconds": ti},
+        "speedup": tc / tw,
+        "steps_saved": rc.iters - rw.iters,
+        "same_eigenvector": {"lambda_rel_diff": abs(rw.lam - rc.lam) / rc.lam,
+                             "x_l2_diff": float(torch.linalg.norm(warm[-1][1] - cold[-1][1]))},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -267,6 +318,9 @@ def main():
         sys.exit(2)
     if args.workload == "batch":
         bench_batch(args)
+        return
+    if args.workload == "warmstart":
+        bench_warmstart(args)
         return
 
     import torch

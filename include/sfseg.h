@@ -269,6 +269,11 @@ int sfseg_unet_forward(sfseg_unet *net, const float *S, int32_t T, int32_t H, in
  * SFSEG_ERR_ZERO_NORM if x^ or the target has zero norm. */
 int sfseg_unet_backward(sfseg_unet *net, const float *target, double *loss);
 
+/* Gradients for an arbitrary loss of the last forward pass, given dL/dx^
+ * (device float32, T x H x W of that pass).  Blocks until done.
+ * SFSEG_ERR_STATE as for sfseg_unet_backward. */
+int sfseg_unet_backward_from(sfseg_unet *net, const float *grad_out);
+
 /* Copy the gradients (exchange layout) to host memory.  Blocks. */
 int sfseg_unet_get_grads(const sfseg_unet *net, float *host_grads, int64_t count);
 

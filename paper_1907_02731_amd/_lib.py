@@ -127,6 +127,8 @@ def lib():
     L.sfseg_unet_forward.restype = ctypes.c_int
     L.sfseg_unet_backward.argtypes = [P, P, ctypes.POINTER(dbl)]
     L.sfseg_unet_backward.restype = ctypes.c_int
+    L.sfseg_unet_backward_from.argtypes = [P, P]
+    L.sfseg_unet_backward_from.restype = ctypes.c_int
     L.sfseg_unet_adam_step.argtypes = [P, dbl, dbl, dbl, dbl, i32]
     L.sfseg_unet_adam_step.restype = ctypes.c_int
     L.sfseg_unet_sync.argtypes = [P]

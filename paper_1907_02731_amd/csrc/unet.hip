@@ -393,12 +393,14 @@ int sfseg_unet_forward(sfseg_unet* n, const float* S, int32_t T, int32_t H, int3
     return SFSEG_OK;
 }
 
-int sfseg_unet_backward(sfseg_unet* n, const float* target, double* loss) {
-    int rc = check_net(n);
-    if (rc) return rc;
-    if (!target) return fail(SFSEG_ERR_INVALID_ARG, "target is NULL");
-    if (!n->training) return fail(SFSEG_ERR_STATE, "network was created without training buffers");
-    if (!n->have_forward) return fail(SFSEG_ERR_STATE, "no forward pass to differentiate");
+}  // extern "C"
+
+namespace {
+
+// Backward pass from dL/dx^: either the cosine loss against `target` (loss
+// written to *loss) or an external gradient `gext`.
+int backward_core(sfseg_unet* n, const float* target, const float* gext, double* loss) {
+    int rc = SFSEG_OK;
     HIP_TRY(hipSetDevice(n->device));
     hipStream_t s = n->stream;
     const int T = n->T, H = n->H, W = n->W;
@@ -425,27 +427,32 @@ int sfseg_unet_backward(sfseg_unet* n, const float* target, double* loss) {
                gba = view(n->gI, Tq, Hq, Wq, 64, 0), gp2 = view(n->gJ, Tq, Hq, Wq, 32, 0);
 
     // loss and its scale factors
-    hipLaunchKernelGGL(sfseg::unet::loss_sums, dim3(kRedBlocks), dim3(256), 0, s, n->xh, target, nv,
-                       n->dpart);
-    HIP_TRY(hipGetLastError());
-    HIP_TRY(hipMemcpyAsync(n->h_dpart, n->dpart, sizeof(double) * 3 * kRedBlocks,
-                           hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    double dot = 0.0, xx = 0.0, tt = 0.0;
-    for (int b = 0; b < kRedBlocks; ++b) {
-        dot += n->h_dpart[3 * b];
-        xx += n->h_dpart[3 * b + 1];
-        tt += n->h_dpart[3 * b + 2];
+    double coef0 = 0.0, coef1 = 0.0;
+    if (!gext) {
+        hipLaunchKernelGGL(sfseg::unet::loss_sums, dim3(kRedBlocks), dim3(256), 0, s, n->xh, target,
+                           nv, n->dpart);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(n->h_dpart, n->dpart, sizeof(double) * 3 * kRedBlocks,
+                               hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        double dot = 0.0, xx = 0.0, tt = 0.0;
+        for (int b = 0; b < kRedBlocks; ++b) {
+            dot += n->h_dpart[3 * b];
+            xx += n->h_dpart[3 * b + 1];
+            tt += n->h_dpart[3 * b + 2];
+        }
+        const double nx = sqrt(xx), nt = sqrt(tt);
+        if (!(nx > 0.0) || !(nt > 0.0) || !isfinite(dot))
+            return fail(SFSEG_ERR_ZERO_NORM, "network output or target has zero or non-finite norm");
+        const double cosv = dot / (nx * nt);
+        if (loss) *loss = 1.0 - cosv;
+        coef0 = 1.0 / (nx * nt);
+        coef1 = cosv / (nx * nx);
     }
-    const double nx = sqrt(xx), nt = sqrt(tt);
-    if (!(nx > 0.0) || !(nt > 0.0) || !isfinite(dot))
-        return fail(SFSEG_ERR_ZERO_NORM, "network output or target has zero or non-finite norm");
-    const double cosv = dot / (nx * nt);
-    if (loss) *loss = 1.0 - cosv;
     const float* w = n->w;
     hipLaunchKernelGGL(sfseg::unet::head_bwd, dim3(kRedBlocks), dim3(256), 0, s, d1,
-                       w + layer_offset(HEAD), n->z, n->xh, target, 1.0 / (nx * nt), cosv / (nx * nx),
-                       gd1, n->dpart);
+                       w + layer_offset(HEAD), n->z, n->xh, target, gext, coef0, coef1, gd1,
+                       n->dpart);
     HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(sfseg::unet::sum_partials, dim3(1), dim3(64), 0, s, n->dpart, kRedBlocks, 17,
                        n->g + layer_offset(HEAD));
@@ -489,6 +496,32 @@ int sfseg_unet_backward(sfseg_unet* n, const float* target, double* loss) {
     if ((rc = layer_grads(n, ENC1A, ge1a, none, n->in32))) return rc;
     HIP_TRY(hipStreamSynchronize(s));
     return SFSEG_OK;
+}
+
+int check_backward(const sfseg_unet* n) {
+    int rc = check_net(n);
+    if (rc) return rc;
+    if (!n->training) return fail(SFSEG_ERR_STATE, "network was created without training buffers");
+    if (!n->have_forward) return fail(SFSEG_ERR_STATE, "no forward pass to differentiate");
+    return SFSEG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sfseg_unet_backward(sfseg_unet* n, const float* target, double* loss) {
+    int rc = check_backward(n);
+    if (rc) return rc;
+    if (!target) return fail(SFSEG_ERR_INVALID_ARG, "target is NULL");
+    return backward_core(n, target, nullptr, loss);
+}
+
+int sfseg_unet_backward_from(sfseg_unet* n, const float* grad_out) {
+    int rc = check_backward(n);
+    if (rc) return rc;
+    if (!grad_out) return fail(SFSEG_ERR_INVALID_ARG, "grad_out is NULL");
+    return backward_core(n, nullptr, grad_out, nullptr);
 }
 
 int sfseg_unet_adam_step(sfseg_unet* n, double lr, double beta1, double beta2, double eps,

@@ -467,13 +467,15 @@ __global__ void loss_sums(const float* __restrict__ xh, const float* __restrict_
     if (threadIdx.x < 3) part[3 * blockIdx.x + threadIdx.x] = sm[threadIdx.x][0];
 }
 
-// Gradient through loss, softplus and head.  coef = (1 / (|xh| |t|), cos / |xh|^2):
+// Gradient through loss, softplus and head.  dL/dxh is gext[v] when gext is
+// given, else that of the cosine loss with coef = (1 / (|xh| |t|), cos / |xh|^2):
 //   dL/dxh = -(t coef0 - xh coef1);  gz = dL/dxh * sigmoid(z);
 //   g_d1[v][c] = gz wh[c] (d1 > 0);  head partials (FP64): sum gz d1[c], sum gz
 //   in hp[block * 17 + c].
 __global__ void head_bwd(View d1, const float* __restrict__ wh, const float* __restrict__ z,
-                         const float* __restrict__ xh, const float* __restrict__ tg, double coef0,
-                         double coef1, View gd1, double* __restrict__ hp) {
+                         const float* __restrict__ xh, const float* __restrict__ tg,
+                         const float* __restrict__ gext, double coef0, double coef1, View gd1,
+                         double* __restrict__ hp) {
     __shared__ double sm[17][256];
     double acc[17];
 #pragma unroll
@@ -481,7 +483,7 @@ __global__ void head_bwd(View d1, const float* __restrict__ wh, const float* __r
     const int64_t n = (int64_t)d1.T * d1.H * d1.W;
     for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
          v += (int64_t)gridDim.x * blockDim.x) {
-        const float gx = (float)(-(tg[v] * coef0 - xh[v] * coef1));
+        const float gx = gext ? gext[v] : (float)(-(tg[v] * coef0 - xh[v] * coef1));
         const float gz = gx / (1.f + expf(-z[v]));
 #pragma unroll
         for (int c = 0; c < 16; ++c) {

@@ -5,7 +5,9 @@
 1. draws ``n`` seeded synthetic clips of 32 x 128 x 224 (seeds 40000 + i),
 2. computes each clip's principal eigenvector with the plain method (batched
    power iteration to delta < 1e-6) as the training target,
-3. trains the network with Adam on 1 - cos(x^, x*), one clip per step,
+3. trains the network with Adam on 1 - cos(x^, x*) or, with --loss spectral,
+   on 1 - cos(M^k x^, x*) (the error left after k power steps), one clip per
+   step,
 4. saves the float32 parameters (numpy .npy, exchange layout of sfseg.h),
 5. on held-out full-resolution clips (70 x 480 x 854, seeds 1001 ...) runs the
    plain method from S (cold) and from the network's estimate (warm) to
@@ -27,7 +29,8 @@ import torch
 
 from .synth import full_clip
 from .warmstart import (GRAPH, TRAIN_SHAPE, WEIGHTS, UNet, eigenvector_targets, he_init,
-                        save_params, solve_cold, solve_warm, train, training_clips)
+                        load_params, save_params, solve_cold, solve_warm, train, train_spectral,
+                        training_clips)
 
 
 def log(msg: str) -> None:
@@ -61,6 +64,10 @@ def main(argv=None):
     ap.add_argument("--out", default=WEIGHTS)
     ap.add_argument("--eval-seeds", default="1001,1002")
     ap.add_argument("--log-every", type=int, default=200)
+    ap.add_argument("--loss", choices=["cos", "spectral"], default="cos",
+                    help="cos: 1 - cos(x^, x*); spectral: 1 - cos(M^k x^, x*)")
+    ap.add_argument("--k", type=int, default=32, help="power steps inside the spectral loss")
+    ap.add_argument("--init", default="", help="start from these parameters (.npy)")
     args = ap.parse_args(argv)
 
     t0 = time.time()
@@ -74,9 +81,15 @@ def main(argv=None):
     log(f"data ready ({time.time() - t0:.0f}s)")
 
     with UNet(TRAIN_SHAPE, training=True) as net:
-        net.set_params(he_init(args.seed))
-        losses = train(net, inputs, targets, epochs=args.epochs, lr=args.lr,
-                       lr_final=args.lr_final, seed=args.seed, log=log, log_every=args.log_every)
+        net.set_params(load_params(args.init) if args.init else he_init(args.seed))
+        if args.loss == "cos":
+            losses = train(net, inputs, targets, epochs=args.epochs, lr=args.lr,
+                           lr_final=args.lr_final, seed=args.seed, log=log,
+                           log_every=args.log_every)
+        else:
+            losses = train_spectral(net, inputs, targets, k=args.k, epochs=args.epochs,
+                                    lr=args.lr, lr_final=args.lr_final, seed=args.seed, log=log,
+                                    log_every=args.log_every)
         params = net.get_params()
     save_params(params, args.out)
     log(f"saved {args.out}; final mean loss {np.mean(losses[-200:]):.5f} ({time.time() - t0:.0f}s)")

@@ -134,6 +134,14 @@ class UNet:
                                                       ctypes.byref(loss)), "sfseg_unet_backward")
         return float(loss.value)
 
+    def backward_from(self, grad_out: torch.Tensor) -> None:
+        """Gradients of an arbitrary loss given dL/dx^ of the last forward pass."""
+        grad_out = grad_out.contiguous()
+        with torch.cuda.device(self.device):
+            self.stream.wait_stream(torch.cuda.current_stream())
+            _lib.check(_lib.lib().sfseg_unet_backward_from(self._h(), grad_out.data_ptr()),
+                       "sfseg_unet_backward_from")
+
     def adam_step(self, lr: float, step: int, beta1: float = 0.9, beta2: float = 0.999,
                   eps: float = 1e-8) -> None:
         with torch.cuda.device(self.device):
@@ -192,6 +200,53 @@ def train(net: UNet, inputs: Sequence[torch.Tensor], targets: Sequence[torch.Ten
             if log and (step % log_every == 0 or step == total):
                 log(f"step {step}/{total} loss(mean of last {log_every}) "
                     f"{np.mean(losses[-log_every:]):.5f} rate {rate:.2e} {time.time() - t0:.1f}s")
+    return losses
+
+
+def train_spectral(net: UNet, inputs: Sequence[torch.Tensor], targets: Sequence[torch.Tensor], *,
+                   k: int = 32, graph: Dict = GRAPH, epochs: int = 1, lr: float = 1e-3,
+                   lr_final: float = 1e-4, seed: int = 0, log=None, log_every: int = 100,
+                   params0: Optional[np.ndarray] = None) -> List[float]:
+    """Adam on the error that survives k power-iteration steps:
+
+        L = 1 - cos(M^k x^, x*),   dL/dx^ = M^k dL/dy   (M is symmetric),
+
+    with M the clip's graph applied by the library (sfseg_apply).  Components
+    of x^ along fast-decaying eigenvectors are damped by (lambda_i /
+    lambda_1)^k before the loss sees them, so the network is trained on the
+    slow components, the ones that set the number of steps.  Intermediate
+    vectors are rescaled by their norms; the same scalars divide the backward
+    chain, so the gradient is exact."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    total = epochs * len(inputs)
+    losses: List[float] = []
+    step = 0
+    t0 = time.time()
+    with Solver(inputs[0], **graph) as sol:
+        for _ in range(epochs):
+            for i in rng.permutation(len(inputs)):
+                step += 1
+                rate = lr_final + 0.5 * (lr - lr_final) * (1 + math.cos(math.pi * (step - 1) / total))
+                sol.set_features(inputs[i])
+                y = net.forward(inputs[i])
+                scale = []
+                for _ in range(k):
+                    y = sol.apply(y)
+                    s_ = torch.linalg.norm(y)
+                    scale.append(s_)
+                    y = y / s_
+                t = targets[i]
+                ny, nt = torch.linalg.norm(y), torch.linalg.norm(t)
+                c = torch.dot(y.ravel(), t.ravel()) / (ny * nt)
+                g = -(t / (ny * nt) - c * y / (ny * ny))
+                for s_ in reversed(scale):
+                    g = sol.apply(g) / s_
+                net.backward_from(g)
+                net.adam_step(rate, step)
+                losses.append(1.0 - float(c))
+                if log and (step % log_every == 0 or step == total):
+                    log(f"step {step}/{total} loss after {k} steps (mean of last {log_every}) "
+                        f"{np.mean(losses[-log_every:]):.6f} rate {rate:.2e} {time.time() - t0:.1f}s")
     return losses
 
 
