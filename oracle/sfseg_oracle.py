@@ -46,7 +46,7 @@ import scipy.sparse as sp
 
 __all__ = [
     "OracleConfig", "unary_weights", "gaussian_taps", "spacetime_kernel",
-    "build_adjacency", "build_adjacency_exact", "power_iteration",
+    "build_adjacency", "build_adjacency_exact", "build_adjacency_multi", "power_iteration",
     "ZeroNormError",
 ]
 
@@ -152,6 +152,23 @@ def build_adjacency(S: np.ndarray, F: Optional[np.ndarray], cfg: OracleConfig) -
     """
     alpha = float(cfg.alpha)
     return _build(S, F, cfg, lambda dF: 1.0 - alpha * dF * dF)
+
+
+def build_adjacency_multi(S: np.ndarray, Fs: np.ndarray, cfg: OracleConfig) -> sp.csr_matrix:
+    """Multi-channel adjacency (Sec. 3.3, Eq. (9)): one step with several
+    pairwise feature channels F_1..F_C is the sum of the single-channel steps,
+    so the matrix is the sum over channels of Eq. (2)'s M built with F_c:
+
+        M_ij = w_i w_j [C - alpha sum_c (F_c,i - F_c,j)^2] G(j - i).
+
+    ``Fs`` has shape (C, T, H, W)."""
+    Fs = np.asarray(Fs, dtype=np.float64)
+    if Fs.ndim != 4 or Fs.shape[1:] != np.shape(S):
+        raise ValueError("Fs must be (C, T, H, W) with (T, H, W) the shape of S")
+    M = build_adjacency(S, Fs[0], cfg)
+    for c in range(1, Fs.shape[0]):
+        M = M + build_adjacency(S, Fs[c], cfg)
+    return M.tocsr()
 
 
 def build_adjacency_exact(S: np.ndarray, F: Optional[np.ndarray], cfg: OracleConfig) -> sp.csr_matrix:

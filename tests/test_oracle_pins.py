@@ -412,3 +412,32 @@ def test_planted_axis_transpose_is_caught():
     xt2 = np.ascontiguousarray(np.swapaxes(x, 0, 2))
     bad2 = np.swapaxes((build_adjacency(St2, None, cfg) @ xt2.ravel()).reshape(St2.shape), 0, 2)
     assert not np.allclose(good, bad2, rtol=1e-6)
+
+
+# ---------------------------------------------------------------------------
+# Multiple feature channels (Sec. 3.3, Eq. (9))
+# ---------------------------------------------------------------------------
+def test_multi_channel_two_node_chain_by_hand():
+    from oracle import build_adjacency_multi
+    cfg = OracleConfig(r_t=0, r_s=1, sigma_t=1.0, sigma_s=1.5, alpha=0.7, p=0.5)
+    S = np.array([[[0.25, 0.64]]])
+    Fs = np.array([[[[0.1, 0.4]]], [[[0.9, 0.3]]]])
+    M = build_adjacency_multi(S, Fs, cfg).toarray()
+    w = np.sqrt(S.ravel())
+    g1 = np.exp(-1.0 / (2 * 1.5 ** 2))
+    off = w[0] * w[1] * (2.0 - 0.7 * ((0.1 - 0.4) ** 2 + (0.9 - 0.3) ** 2)) * g1
+    np.testing.assert_allclose(M, [[2 * w[0] ** 2, off], [off, 2 * w[1] ** 2]], rtol=1e-14)
+
+
+def test_multi_channel_equal_channels_scale_the_single_channel_matrix():
+    from oracle import build_adjacency_multi
+    cfg = OracleConfig(r_t=1, r_s=2, sigma_t=1.0, sigma_s=1.0, alpha=1.0, p=0.2)
+    r = np.random.Generator(np.random.PCG64(77))
+    S = r.random((3, 6, 7))
+    F = r.random((3, 6, 7))
+    M1 = build_adjacency(S, F, cfg)
+    M3 = build_adjacency_multi(S, np.stack([F, F, F]), cfg)
+    assert abs(M3 - 3.0 * M1).max() <= 1e-13
+    M2 = build_adjacency_multi(S, np.stack([F, S]), cfg)
+    assert abs(M2 - M2.T).max() == 0.0
+    np.testing.assert_allclose(M2.diagonal(), 2.0 * unary_weights(S, 0.2).ravel() ** 2, rtol=1e-14)
