@@ -44,6 +44,7 @@ extern "C" {
 /* Largest radii the compiled kernels support. */
 #define SFSEG_MAX_RS 8
 #define SFSEG_MAX_RT 4
+#define SFSEG_MAX_FEATURES 2 /* pairwise feature channels (Sec. 3.3) */
 
 typedef struct sfseg_ctx sfseg_ctx; /* opaque; owned by the library */
 
@@ -115,8 +116,8 @@ void sfseg_config_default(sfseg_config *cfg);
 /* Check a configuration without touching the GPU.  Host only. */
 int sfseg_config_validate(const sfseg_config *cfg);
 
-/* Create a context for one clip (Sec. 3: "feature maps in, segmentation
- * out").  Allocates the device buffers, then on `stream` computes w = S^p and
+/* Create a context for one clip (Sec. 3: per-pixel feature maps in, the
+ * principal eigenvector out).  Allocates the device buffers, then on `stream` computes w = S^p and
  * copies F (F == NULL means F = S) and S (the default start vector, Alg. 1
  * initialises X with S) into storage precision.  `stream` is a hipStream_t
  * (NULL = the null stream).  The caller may release S and F once the stream
@@ -125,6 +126,17 @@ int sfseg_config_validate(const sfseg_config *cfg);
  * p > 0.  On success *out owns the context; on failure *out is NULL. */
 int sfseg_create(const sfseg_config *cfg, const float *S, const float *F, void *stream,
                  sfseg_ctx **out);
+
+/* As sfseg_create with n_features pairwise feature channels (Sec. 3.3,
+ * Eq. (9)): one step is the sum of the single-channel steps, i.e. the matrix
+ * is M_ij = w_i w_j [C - alpha sum_c (F_c,i - F_c,j)^2] G(j - i).  F holds the
+ * n_features channels one after another (n_features x T x H x W, device
+ * float32); F == NULL is allowed only for n_features == 1 (F = S).
+ * 1 <= n_features <= SFSEG_MAX_FEATURES; more than one channel needs float32
+ * storage (SFSEG_ERR_UNSUPPORTED otherwise) and is not available in batches.
+ * sfseg_set_features then takes F in the same layout. */
+int sfseg_create_mc(const sfseg_config *cfg, const float *S, const float *F, int32_t n_features,
+                    void *stream, sfseg_ctx **out);
 
 /* Replace the features of an existing context (same shape and config) without
  * reallocating: the prep of sfseg_create, ordered on the context's stream.

@@ -24,7 +24,7 @@ SFSEG_ERR_UNSUPPORTED = -7
 
 SFSEG_F32, SFSEG_BF16, SFSEG_F16 = 0, 1, 2
 DTYPES = {"f32": SFSEG_F32, "bf16": SFSEG_BF16, "f16": SFSEG_F16}
-MAX_RS, MAX_RT = 8, 4
+MAX_RS, MAX_RT, MAX_FEATURES = 8, 4, 2
 
 
 class Config(ctypes.Structure):
@@ -78,6 +78,8 @@ def lib():
     L.sfseg_config_validate.restype = ctypes.c_int
     L.sfseg_create.argtypes = [pcfg, P, P, P, ctypes.POINTER(P)]
     L.sfseg_create.restype = ctypes.c_int
+    L.sfseg_create_mc.argtypes = [pcfg, P, P, ctypes.c_int32, P, ctypes.POINTER(P)]
+    L.sfseg_create_mc.restype = ctypes.c_int
     L.sfseg_set_features.argtypes = [P, P, P]
     L.sfseg_set_features.restype = ctypes.c_int
     L.sfseg_power_iterate.argtypes = [P, P, ctypes.c_int32, ctypes.c_double,

@@ -126,6 +126,12 @@ int run_prep(sfseg_ctx* ctx, const float* S, const float* F) {
     HIP_TRY(hipMemsetAsync(ctx->d_bad, 0, sizeof(int32_t), ctx->stream));
     HIP_TRY(sfseg::launch_prep(ctx->cfg.storage, S, F, ctx->cfg.p, ctx->w, ctx->f, ctx->s0, ctx->L,
                                ctx->d_bad, ctx->ew_grid, ctx->stream));
+    // further feature channels: F holds them one after another
+    const int64_t n = (int64_t)ctx->cfg.T * ctx->cfg.H * ctx->cfg.W;
+    for (int c = 1; c < ctx->nf; ++c)
+        HIP_TRY(sfseg::launch_to_storage(ctx->cfg.storage, F + c * n,
+                                         (char*)ctx->f + c * ctx->L.total * dtype_size(ctx->cfg.storage),
+                                         ctx->L, ctx->ew_grid, ctx->stream));
     HIP_TRY(hipMemcpyAsync(ctx->h_bad, ctx->d_bad, sizeof(int32_t), hipMemcpyDeviceToHost,
                            ctx->stream));
     HIP_TRY(hipStreamSynchronize(ctx->stream));
@@ -219,7 +225,8 @@ int default_plan(sfseg_ctx* ctx, int* shape, int* chunks) {
     const sfseg_config& c = ctx->cfg;
     *shape = 0;
     int occ = 1;
-    HIP_TRY(sfseg::step_max_blocks_per_cu(c.storage, *shape, c.r_s, c.r_t, &occ));
+    HIP_TRY(sfseg::step_max_blocks_per_cu(c.storage, sfseg::kernel_shape(*shape, ctx->nf), c.r_s,
+                                          c.r_t, &occ));
     if (occ < 1) occ = 1;
     const int tiles = ctx->L.tiles_x * ctx->L.tiles_y;
     int ch = ctx->cus * occ / tiles;
@@ -242,7 +249,7 @@ int setup(sfseg_ctx* ctx, const float* S, const float* F) {
     ctx->ew_grid = ctx->cus * 8;
 
     HIP_TRY(hipMalloc(&ctx->w, bytes));
-    HIP_TRY(hipMalloc(&ctx->f, bytes));
+    HIP_TRY(hipMalloc(&ctx->f, bytes * ctx->nf));
     HIP_TRY(hipMalloc(&ctx->s0, bytes));
     HIP_TRY(hipMalloc(&ctx->buf[0], bytes));
     HIP_TRY(hipMalloc(&ctx->buf[1], bytes));
@@ -253,8 +260,9 @@ int setup(sfseg_ctx* ctx, const float* S, const float* F) {
     HIP_TRY(hipHostMalloc((void**)&ctx->h_bad, sizeof(int32_t), hipHostMallocDefault));
     for (auto& e : ctx->ev) HIP_TRY(hipEventCreate(&e));
     // The padding of every volume must hold zeros; nothing ever writes it.
-    void* vols[] = {ctx->w, ctx->f, ctx->s0, ctx->buf[0], ctx->buf[1]};
+    void* vols[] = {ctx->w, ctx->s0, ctx->buf[0], ctx->buf[1]};
     for (void* v : vols) HIP_TRY(hipMemsetAsync(v, 0, bytes, ctx->stream));
+    HIP_TRY(hipMemsetAsync(ctx->f, 0, bytes * ctx->nf, ctx->stream));
     HIP_TRY(hipMemsetAsync(ctx->st, 0, sizeof(DevState), ctx->stream));
     HIP_TRY(hipMemsetAsync(ctx->st_apply, 0, sizeof(DevState), ctx->stream));
 
@@ -271,6 +279,7 @@ int setup(sfseg_ctx* ctx, const float* S, const float* F) {
         p.PT = L.PT;
         p.PL = L.PL;
         p.frame = L.frame;
+        p.fstride = L.total;
         axis_taps(c.r_s, c.sigma_s, p.gs);
         axis_taps(c.r_t, c.sigma_t, p.gt);
         p.alpha = (float)c.alpha;
@@ -314,7 +323,8 @@ int run_init(hipStream_t stream, const sfseg_config& c, const sfseg::Layout& L, 
 int launch_steps(sfseg_ctx* ctx, int first_buf, int count) {
     for (int i = 0; i < count; ++i) {
         const int b = (first_buf + i) & 1;
-        HIP_TRY(sfseg::launch_step(ctx->cfg.storage, ctx->shape, ctx->cfg.r_s, ctx->cfg.r_t,
+        HIP_TRY(sfseg::launch_step(ctx->cfg.storage, sfseg::kernel_shape(ctx->shape, ctx->nf),
+                                   ctx->cfg.r_s, ctx->cfg.r_t,
                                    ctx->params[b], ctx->step_grid, ctx->stream));
     }
     return SFSEG_OK;
@@ -344,15 +354,22 @@ int ensure_graph(sfseg_ctx* ctx) {
 
 extern "C" {
 
-int sfseg_create(const sfseg_config* cfg, const float* S, const float* F, void* stream,
-                 sfseg_ctx** out) {
+int sfseg_create_mc(const sfseg_config* cfg, const float* S, const float* F, int32_t n_features,
+                    void* stream, sfseg_ctx** out) {
     if (!out) return fail(SFSEG_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
     int rc = sfseg_config_validate(cfg);
     if (rc != SFSEG_OK) return rc;
     if (!S) return fail(SFSEG_ERR_INVALID_ARG, "S is NULL");
+    if (n_features < 1 || n_features > SFSEG_MAX_FEATURES)
+        return fail(SFSEG_ERR_INVALID_ARG, "n_features must be 1..%d", SFSEG_MAX_FEATURES);
+    if (n_features > 1 && !F)
+        return fail(SFSEG_ERR_INVALID_ARG, "F must hold the %d feature channels", n_features);
+    if (n_features > 1 && cfg->storage != SFSEG_F32)
+        return fail(SFSEG_ERR_UNSUPPORTED, "several feature channels need float32 storage");
     sfseg_ctx* ctx = new (std::nothrow) sfseg_ctx();
     if (!ctx) return fail(SFSEG_ERR_OOM, "host allocation failed");
+    ctx->nf = n_features;
     ctx->cfg = *cfg;
     ctx->stream = (hipStream_t)stream;
     ctx->n = (int64_t)cfg->T * cfg->H * cfg->W;
@@ -368,10 +385,17 @@ int sfseg_create(const sfseg_config* cfg, const float* S, const float* F, void* 
     return SFSEG_OK;
 }
 
+int sfseg_create(const sfseg_config* cfg, const float* S, const float* F, void* stream,
+                 sfseg_ctx** out) {
+    return sfseg_create_mc(cfg, S, F, 1, stream, out);
+}
+
 int sfseg_set_features(sfseg_ctx* ctx, const float* S, const float* F) {
     if (!ctx) return fail(SFSEG_ERR_INVALID_ARG, "ctx is NULL");
     if (ctx->batch) return fail(SFSEG_ERR_STATE, "batch context: use the sfseg_batch_* calls");
     if (!S) return fail(SFSEG_ERR_INVALID_ARG, "S is NULL");
+    if (ctx->nf > 1 && !F)
+        return fail(SFSEG_ERR_INVALID_ARG, "F must hold the %d feature channels", ctx->nf);
     HIP_TRY(hipSetDevice(ctx->device));
     return run_prep(ctx, S, F);
 }
@@ -490,7 +514,8 @@ int sfseg_apply(sfseg_ctx* ctx, const float* x, float* y) {
     p.x = ctx->apply_in;
     p.y = ctx->apply_out;
     p.st = ctx->st_apply;
-    HIP_TRY(sfseg::launch_step(ctx->cfg.storage, ctx->shape, ctx->cfg.r_s, ctx->cfg.r_t, p,
+    HIP_TRY(sfseg::launch_step(ctx->cfg.storage, sfseg::kernel_shape(ctx->shape, ctx->nf),
+                               ctx->cfg.r_s, ctx->cfg.r_t, p,
                                ctx->step_grid, ctx->stream));
     HIP_TRY(sfseg::launch_from_storage(ctx->cfg.storage, ctx->apply_out, y, ctx->L, ctx->ew_grid,
                                        ctx->stream));

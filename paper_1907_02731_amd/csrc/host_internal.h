@@ -69,6 +69,7 @@ struct sfseg_ctx {
     size_t items_cap = 0;   // capacity of `items` in entries
     sfseg::Layout L{};
     int cus = 0;
+    int nf = 1;             // pairwise feature channels (1 or 2)
     int shape = 0;          // step-kernel block shape (sfseg::step_threads)
     int chunks = 1;         // runs of frames per tile
     int step_grid = 0;

@@ -142,10 +142,12 @@ __global__ __launch_bounds__(256) void from_storage_kernel(const TS* __restrict_
 
 }  // namespace
 
+// `shape` is a kernel shape (kernel_shape): 0..1 for every storage type,
+// 2..3 (two feature channels) for float32 only.
 hipError_t launch_step(int dtype, int shape, int rs, int rt, const StepParams& p, int grid,
                        hipStream_t s) {
-    if (shape < 0 || shape >= STEP_SHAPES || rs < 0 || rs > SFSEG_MAX_RS || rt < 0 ||
-        rt > SFSEG_MAX_RT)
+    if (shape < 0 || shape >= 2 * STEP_SHAPES || (shape >= STEP_SHAPES && dtype != SFSEG_F32) ||
+        rs < 0 || rs > SFSEG_MAX_RS || rt < 0 || rt > SFSEG_MAX_RT)
         return hipErrorInvalidValue;
     switch (dtype) {
         case SFSEG_F32: return launch_step_f32(shape, rs, rt, p, grid, s);
@@ -181,8 +183,8 @@ hipError_t batch_max_blocks_per_cu(int dtype, int shape, int rs, int rt, int* bl
 }
 
 hipError_t step_max_blocks_per_cu(int dtype, int shape, int rs, int rt, int* blocks) {
-    if (shape < 0 || shape >= STEP_SHAPES || rs < 0 || rs > SFSEG_MAX_RS || rt < 0 ||
-        rt > SFSEG_MAX_RT)
+    if (shape < 0 || shape >= 2 * STEP_SHAPES || (shape >= STEP_SHAPES && dtype != SFSEG_F32) ||
+        rs < 0 || rs > SFSEG_MAX_RS || rt < 0 || rt > SFSEG_MAX_RT)
         return hipErrorInvalidValue;
     switch (dtype) {
         case SFSEG_F32: return occ_step_f32(shape, rs, rt, blocks);

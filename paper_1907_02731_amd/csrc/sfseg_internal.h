@@ -55,6 +55,7 @@ struct StepParams {
     const int4* items;   // per logical block: tile origin x, y (picture coords), frames [z, w)
     int32_t T, Wp, PT, PL;
     int64_t frame;
+    int64_t fstride;  // elements between consecutive feature channels of f
     float gs[SFSEG_MAX_RS + 1];  // spatial taps g_s[d], d = 0..r_s
     float gt[SFSEG_MAX_RT + 1];  // temporal taps g_t[d], d = 0..r_t
     float alpha;
@@ -91,6 +92,9 @@ constexpr int TILE_Y = 16;
 // Block shapes of the step kernel: 0 = 256 threads, 4 outputs each along x;
 // 1 = 512 threads, 2 outputs each.
 constexpr int STEP_SHAPES = 2;
+// Kernel variant of a plan: the block shape, and + 2 for two feature channels
+// (float32 storage only).
+constexpr int kernel_shape(int shape, int nf) { return shape + 2 * (nf - 1); }
 constexpr int step_threads(int shape) { return shape == 0 ? 256 : 512; }
 
 hipError_t launch_step(int dtype, int shape, int rs, int rt, const StepParams& p, int grid,

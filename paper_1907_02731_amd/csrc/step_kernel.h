@@ -287,16 +287,20 @@ constexpr int TX = TILE_X, TY = TILE_Y;
 constexpr int round4(int v) { return (v + 3) / 4 * 4; }
 
 // Block shapes: PX outputs per thread along x, so TX / PX thread columns and
-// NT = 16 * TX / PX threads.
-template <int PX_>
+// NT = 16 * TX / PX threads; NF pairwise feature channels (Sec. 3.3): the
+// filter then carries 1 + 2 NF fields, u and F_c u, F_c^2 u per channel.
+template <int PX_, int NF_ = 1>
 struct Shape {
     static constexpr int PX = PX_;
+    static constexpr int NF = NF_;
     static constexpr int NSEG = TX / PX;
     static constexpr int NT = NSEG * TY;
     static constexpr int NWAVES = NT / 64;
 };
 using ShapeWide = Shape<4>;  // 256 threads
 using ShapeDeep = Shape<2>;  // 512 threads
+using ShapeWide2 = Shape<4, 2>;
+using ShapeDeep2 = Shape<2, 2>;
 
 // Per input frame a block runs two phases separated by a barrier:
 //   Y: the y pass over the tile plus its x halo (64 + 2 r_s columns).  Every
@@ -315,6 +319,9 @@ using ShapeDeep = Shape<2>;  // 512 threads
 template <typename TS, int RS, int RT, typename SH>
 struct Geom {
     static constexpr int NT = SH::NT, PX = SH::PX, NSEG = SH::NSEG, NWAVES = SH::NWAVES;
+    static constexpr int NF = SH::NF;                // pairwise feature channels
+    static constexpr int NFLD = 1 + 2 * NF;          // filtered fields
+    static constexpr int NARR = 2 + NF;              // arrays read: x, w, F_1..F_NF
     static constexpr int ES = (int)sizeof(TS);
     static constexpr int RSA = round4(RS);           // halo rounded to 16-byte columns
     static constexpr int IW = TX + 2 * RS;           // y-pass columns: tile plus halo
@@ -337,13 +344,13 @@ struct Geom {
     // from the region while it is there) when that still lets two blocks share
     // a CU; otherwise the output frame's values are read from memory.
     static constexpr int RT1 = RT + 1;                // frames in the own-value ring
-    static constexpr int LDS_BASE = 3 * RAWE * ES + 3 * TY * MP * 4;
-    static constexpr bool OWN_LDS = LDS_BASE + RT1 * 3 * TY * TX * ES <= 80 * 1024;
+    static constexpr int LDS_BASE = NARR * RAWE * ES + NFLD * TY * MP * 4;
+    static constexpr bool OWN_LDS = LDS_BASE + RT1 * NARR * TY * TX * ES <= 80 * 1024;
     // Waves per SIMD the register budget is set for (the second launch-bounds
     // argument): with the own ring in LDS two blocks share a CU, so two waves
     // per SIMD (for 256-thread blocks); otherwise three when the register ring
     // is small enough.
-    static constexpr int RING = NR * 3 * PX;
+    static constexpr int RING = NR * NFLD * PX;
     static constexpr int MINW = OWN_LDS ? 2 * NT / 256 : (RING <= 84 ? 3 : 2);
     static_assert(NS >= 1 && NS * EXT <= 64 && NS + 1 <= NWAVES, "y-pass lane mapping");
     static_assert(NS * PY >= TY && PY <= TY, "segments cover the tile rows");
@@ -358,11 +365,11 @@ template <typename TS, int RS, int RT, typename SH>
 struct StepLds {
     using G = Geom<TS, RS, RT, SH>;
     union {
-        TS raw[3][G::RAWE];
+        TS raw[G::NARR][G::RAWE];
         double fin[G::NT];
     } __attribute__((aligned(16)));
-    float mid3[3][TY * G::MP] __attribute__((aligned(16)));
-    TS own[G::OWN_LDS ? G::RT1 : 1][3][G::OWN_LDS ? TY * TX : 4] __attribute__((aligned(16)));
+    float mid3[G::NFLD][TY * G::MP] __attribute__((aligned(16)));
+    TS own[G::OWN_LDS ? G::RT1 : 1][G::NARR][G::OWN_LDS ? TY * TX : 4] __attribute__((aligned(16)));
 };
 
 // One work item: the 64 x 16 tile at picture origin (tx0, ty0) of one clip,
@@ -377,16 +384,16 @@ struct StepLds {
 // filter, combine with the own x, w, F of frame t - r_t, and reduce.
 template <typename TS, int RS, int RT, typename SH>
 __device__ __forceinline__ void run_item(const TS* __restrict__ X, const TS* __restrict__ Wt,
-                                         const TS* __restrict__ Fv, TS* __restrict__ Y, int T,
-                                         int Wp, int PT, int PL, int64_t frame, int tx0, int ty0,
-                                         int ta, int tb, const float* gs, const float* gt,
-                                         float alpha, StepLds<TS, RS, RT, SH>& lds, double& syy,
-                                         double& syx) {
+                                         const TS* __restrict__ Fv, int64_t fstride,
+                                         TS* __restrict__ Y, int T, int Wp, int PT, int PL,
+                                         int64_t frame, int tx0, int ty0, int ta, int tb,
+                                         const float* gs, const float* gt, float alpha,
+                                         StepLds<TS, RS, RT, SH>& lds, double& syy, double& syx) {
     using G = Geom<TS, RS, RT, SH>;
     constexpr int NT = G::NT, PX = G::PX, NSEG = G::NSEG, IW = G::IW, EXT = G::EXT,
                   NS = G::NS, PY = G::PY, YW = G::YW, XWA = G::XWA, MP = G::MP, NR = G::NR,
                   RSA = G::RSA, IWA = G::IWA, CPR = G::CPR, NCH = G::NCH, NDMA = G::NDMA,
-                  RAWE = G::RAWE;
+                  RAWE = G::RAWE, NF = G::NF, NFLD = G::NFLD, NARR = G::NARR;
     constexpr int ES = (int)sizeof(TS);
     if (tb <= ta) return;
     const uint32_t frame_bytes = (uint32_t)(frame * ES);
@@ -414,7 +421,8 @@ __device__ __forceinline__ void run_item(const TS* __restrict__ X, const TS* __r
     // the clip are zeros.
     auto load_region_array = [&](int t, int a) {
         if (t >= 0 && t < T) {
-            const __amdgpu_buffer_rsrc_t rr = rsrc(a == 0 ? X : (a == 1 ? Wt : Fv), t);
+            const __amdgpu_buffer_rsrc_t rr =
+                rsrc(a == 0 ? X : (a == 1 ? Wt : Fv + (int64_t)(a - 2) * fstride), t);
 #pragma unroll
             for (int r = 0; r < NDMA; ++r) {
                 if (r * NT + tid < NCH)
@@ -451,7 +459,7 @@ __device__ __forceinline__ void run_item(const TS* __restrict__ X, const TS* __r
         if constexpr (G::OWN_LDS) {
             const int slot = t % G::RT1;
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
+            for (int a = 0; a < NARR; ++a) {
                 if constexpr (PX * ES == 16) {
                     *reinterpret_cast<u32x4*>(&lds.own[slot][a][town]) =
                         *reinterpret_cast<const u32x4*>(&lds.raw[a][rown]);
@@ -465,28 +473,31 @@ __device__ __forceinline__ void run_item(const TS* __restrict__ X, const TS* __r
             }
         }
     };
-    float qX[PX], qW[PX], qF[PX];  // own x, w, F of the output frame
+    float qX[PX], qW[PX], qF[NF][PX];  // own x, w, F_c of the output frame
     auto read_own = [&](int t) {
         const int slot = t % G::RT1;
 #pragma unroll
         for (int i = 0; i < PX; ++i) {
             qX[i] = (float)lds.own[slot][0][town + i];
             qW[i] = (float)lds.own[slot][1][town + i];
-            qF[i] = (float)lds.own[slot][2][town + i];
+#pragma unroll
+            for (int c = 0; c < NF; ++c) qF[c][i] = (float)lds.own[slot][2 + c][town + i];
         }
     };
     auto load_own = [&](int t) {
-        const __amdgpu_buffer_rsrc_t rx = rsrc(X, t), rw = rsrc(Wt, t), rf = rsrc(Fv, t);
+        const __amdgpu_buffer_rsrc_t rx = rsrc(X, t), rw = rsrc(Wt, t);
         Stor<TS>::template bloadn<PX>(rx, ooff, qX);
         Stor<TS>::template bloadn<PX>(rw, ooff, qW);
-        Stor<TS>::template bloadn<PX>(rf, ooff, qF);
+#pragma unroll
+        for (int c = 0; c < NF; ++c)
+            Stor<TS>::template bloadn<PX>(rsrc(Fv + (int64_t)c * fstride, t), ooff, qF[c]);
     };
 
-    float ring[NR][3][PX];  // x/y-filtered fields of the last NR frames
+    float ring[NR][NFLD][PX];  // x/y-filtered fields of the last NR frames
 #pragma unroll
     for (int j = 0; j < NR; ++j)
 #pragma unroll
-        for (int f = 0; f < 3; ++f)
+        for (int f = 0; f < NFLD; ++f)
 #pragma unroll
             for (int i = 0; i < PX; ++i) ring[j][f][i] = 0.f;
     float yv[PX];          // outputs waiting to be stored
@@ -497,7 +508,7 @@ __device__ __forceinline__ void run_item(const TS* __restrict__ X, const TS* __r
     const int n_in = (tb - ta) + 2 * RT;
     const int n_steps = (n_in + NR - 1) / NR * NR;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) load_region_array(ta - RT, a);
+    for (int a = 0; a < NARR; ++a) load_region_array(ta - RT, a);
 
     for (int s0 = 0; s0 < n_steps; s0 += NR) {
 #pragma unroll
@@ -517,23 +528,29 @@ __device__ __forceinline__ void run_item(const TS* __restrict__ X, const TS* __r
             if (yact) {
                 const TS* rx = &lds.raw[0][ybase];
                 const TS* rw = &lds.raw[1][ybase];
-                const TS* rf = &lds.raw[2][ybase];
-                float a0[PY], a1[PY], a2[PY];
+                float acc[NFLD][PY];
 #pragma unroll
-                for (int i = 0; i < PY; ++i) a0[i] = a1[i] = a2[i] = 0.f;
+                for (int f = 0; f < NFLD; ++f)
+#pragma unroll
+                    for (int i = 0; i < PY; ++i) acc[f][i] = 0.f;
 #pragma unroll
                 for (int k = 0; k < YW; ++k) {
-                    const float u = (float)rw[k * IWA] * (float)rx[k * IWA];
-                    const float fv = (float)rf[k * IWA];
-                    const float v = fv * u, z = fv * v;
+                    // fields: u, then F_c u and F_c^2 u for each channel c
+                    float fld[NFLD];
+                    fld[0] = (float)rw[k * IWA] * (float)rx[k * IWA];
+#pragma unroll
+                    for (int c = 0; c < NF; ++c) {
+                        const float fv = (float)lds.raw[2 + c][ybase + k * IWA];
+                        fld[1 + 2 * c] = fv * fld[0];
+                        fld[2 + 2 * c] = fv * fld[1 + 2 * c];
+                    }
 #pragma unroll
                     for (int i = 0; i < PY; ++i) {
                         const int d = k - i - RS;  // tap offset, constant once unrolled
                         if (d >= -RS && d <= RS) {
                             const float g = gs[d < 0 ? -d : d];
-                            a0[i] = fmaf(g, u, a0[i]);
-                            a1[i] = fmaf(g, v, a1[i]);
-                            a2[i] = fmaf(g, z, a2[i]);
+#pragma unroll
+                            for (int f = 0; f < NFLD; ++f) acc[f][i] = fmaf(g, fld[f], acc[f][i]);
                         }
                     }
                 }
@@ -541,9 +558,8 @@ __device__ __forceinline__ void run_item(const TS* __restrict__ X, const TS* __r
                 for (int i = 0; i < PY; ++i) {
                     if (i >= yskip) {
                         const int o = (ys + i) * MP + ycol;
-                        lds.mid3[0][o] = a0[i];
-                        lds.mid3[1][o] = a1[i];
-                        lds.mid3[2][o] = a2[i];
+#pragma unroll
+                        for (int f = 0; f < NFLD; ++f) lds.mid3[f][o] = acc[f][i];
                     }
                 }
             }
@@ -554,8 +570,8 @@ __device__ __forceinline__ void run_item(const TS* __restrict__ X, const TS* __r
             // ---- X phase: filter along x into ring slot j; the region loads
             // of frame t_in + 1 are issued one array per field ----
 #pragma unroll
-            for (int f = 0; f < 3; ++f) {
-                load_region_array(t_in + 1, f);
+            for (int f = 0; f < NFLD; ++f) {
+                if (f < NARR) load_region_array(t_in + 1, f);
                 float win[XWA];
                 const float* src = &lds.mid3[f][orow * MP + ocol];
                 if constexpr (PX % 4 == 0) {
@@ -589,15 +605,24 @@ __device__ __forceinline__ void run_item(const TS* __restrict__ X, const TS* __r
                 if constexpr (G::OWN_LDS) read_own(t_out);
 #pragma unroll
                 for (int i = 0; i < PX; ++i) {
-                    float A = 0.f, B = 0.f, C = 0.f;
+                    float tf[NFLD];  // A = G * u, then C_c = G * (F_c u), B_c = G * (F_c^2 u)
+#pragma unroll
+                    for (int f = 0; f < NFLD; ++f) tf[f] = 0.f;
 #pragma unroll
                     for (int m = 0; m < NR; ++m) {
                         const int slot = (j + 1 + m) % NR;  // constant once unrolled
-                        A = fmaf(gt[m], ring[slot][0][i], A);  // G * u
-                        C = fmaf(gt[m], ring[slot][1][i], C);  // G * (F u)
-                        B = fmaf(gt[m], ring[slot][2][i], B);  // G * (F^2 u)
+#pragma unroll
+                        for (int f = 0; f < NFLD; ++f) tf[f] = fmaf(gt[m], ring[slot][f][i], tf[f]);
                     }
-                    const float E = fmaf(-alpha, fmaf(qF[i], fmaf(qF[i], A, -2.f * C), B), A);
+                    const float A = tf[0];
+                    float q = 0.f;  // sum_c F_c (F_c A - 2 C_c) + B_c
+#pragma unroll
+                    for (int c = 0; c < NF; ++c) {
+                        const float t_c = fmaf(qF[c][i], fmaf(qF[c][i], A, -2.f * tf[1 + 2 * c]),
+                                               tf[2 + 2 * c]);
+                        q = c == 0 ? t_c : q + t_c;
+                    }
+                    const float E = fmaf(-alpha, q, (float)NF * A);
                     const float yq = Stor<TS>::rnd(qW[i] * E);
                     yv[i] = yq;
                     syy = fma((double)yq, (double)yq, syy);
@@ -635,9 +660,9 @@ __global__ __launch_bounds__(SH::NT, (Geom<TS, RS, RT, SH>::MINW)) void step_ker
     const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
     const int4 item = p.items[lb];  // tile origin (picture coords) and frame range
     double syy = 0.0, syx = 0.0;
-    run_item<TS, RS, RT, SH>((const TS*)p.x, (const TS*)p.w, (const TS*)p.f, (TS*)p.y, p.T, p.Wp,
-                             p.PT, p.PL, p.frame, item.x, item.y, item.z, item.w, gs, gt, p.alpha,
-                             lds, syy, syx);
+    run_item<TS, RS, RT, SH>((const TS*)p.x, (const TS*)p.w, (const TS*)p.f, p.fstride,
+                             (TS*)p.y, p.T, p.Wp, p.PT, p.PL, p.frame, item.x, item.y, item.z,
+                             item.w, gs, gt, p.alpha, lds, syy, syx);
 
     if (block_partials_and_ticket<NT>(syy, syx, p.partials, lb, &st->ticket, (uint32_t)gridDim.x)) {
         const double tyy = fixed_order_sum<NT>(p.partials, gridDim.x, 0, lds.fin);
@@ -703,7 +728,7 @@ __global__ __launch_bounds__(SH::NT, (Geom<TS, RS, RT, SH>::MINW)) void batch_st
         for (int m = 0; m < NR; ++m) gt[m] = p.gt[m < RT ? RT - m : m - RT] * c;
         double syy = 0.0, syx = 0.0;
         run_item<TS, RS, RT, SH>((const TS*)cl->buf[p.parity], (const TS*)cl->w,
-                                 (const TS*)cl->f, (TS*)cl->buf[1 - p.parity], cl->T, cl->Wp,
+                                 (const TS*)cl->f, 0, (TS*)cl->buf[1 - p.parity], cl->T, cl->Wp,
                                  cl->PT, cl->PL, cl->frame, item.y & 0xffff, item.y >> 16, item.z,
                                  item.w, gs, gt, p.alpha, lds, syy, syx);
         if (block_partials_and_ticket<NT>(syy, syx, p.partials, it, &st->ticket,
@@ -775,6 +800,26 @@ template <typename TS, typename SH, int... RSs>
 void fill_rs(StepFns* t, std::integer_sequence<int, RSs...>) {
     (fill_rt<TS, SH, RSs>(t, std::make_integer_sequence<int, SFSEG_MAX_RT + 1>{}), ...);
 }
+
+// Step kernels only (no batched form) for two feature channels.
+template <typename TS, typename SH, int RS, int... RTs>
+void fill_rt_step(StepFns* t, std::integer_sequence<int, RTs...>) {
+    ((t[RS * (SFSEG_MAX_RT + 1) + RTs] =
+          StepFns{&launch_step_t<TS, RS, RTs, SH>, &occ_step_t<TS, RS, RTs, SH>, nullptr, nullptr}),
+     ...);
+}
+template <typename TS, typename SH, int... RSs>
+void fill_rs_step(StepFns* t, std::integer_sequence<int, RSs...>) {
+    (fill_rt_step<TS, SH, RSs>(t, std::make_integer_sequence<int, SFSEG_MAX_RT + 1>{}), ...);
+}
+template <typename TS>
+struct StepTable2 {
+    StepFns fns[NSHAPES][NCOMB];
+    StepTable2() {
+        fill_rs_step<TS, ShapeWide2>(fns[0], std::make_integer_sequence<int, SFSEG_MAX_RS + 1>{});
+        fill_rs_step<TS, ShapeDeep2>(fns[1], std::make_integer_sequence<int, SFSEG_MAX_RS + 1>{});
+    }
+};
 
 template <typename TS>
 struct StepTable {

@@ -61,15 +61,19 @@ class Solver:
         self.device = S.device
         self.cfg = _lib.make_config(*self.shape, r_t=r_t, r_s=r_s, sigma_t=sigma_t,
                                     sigma_s=sigma_s, alpha=alpha, p=p, storage=storage)
+        # F: (T, H, W) for one feature channel, (C, T, H, W) for C channels (Eq. (9))
+        self.n_features = 1 if F is None or F.dim() == 3 else int(F.shape[0])
+        self.f_shape = self.shape if self.n_features == 1 and (F is None or F.dim() == 3) \
+            else (self.n_features,) + self.shape
         ps = _dev_ptr(S, "S", self.shape)
-        pf = _dev_ptr(F, "F", self.shape)
+        pf = _dev_ptr(F, "F", self.f_shape)
         self.stream = stream if stream is not None else torch.cuda.Stream(device=S.device)
         self._ctx = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             self.stream.wait_stream(torch.cuda.current_stream())
-            _lib.check(L.sfseg_create(ctypes.byref(self.cfg), ps, pf,
-                                      ctypes.c_void_p(self.stream.cuda_stream),
-                                      ctypes.byref(self._ctx)), "sfseg_create")
+            _lib.check(L.sfseg_create_mc(ctypes.byref(self.cfg), ps, pf, self.n_features,
+                                         ctypes.c_void_p(self.stream.cuda_stream),
+                                         ctypes.byref(self._ctx)), "sfseg_create_mc")
 
     # -- context management ------------------------------------------------
     def close(self) -> None:
@@ -98,7 +102,7 @@ class Solver:
     # -- entry points --------------------------------------------------------
     def set_features(self, S: torch.Tensor, F: Optional[torch.Tensor] = None) -> None:
         ps = _dev_ptr(S, "S", self.shape)
-        pf = _dev_ptr(F, "F", self.shape)
+        pf = _dev_ptr(F, "F", self.f_shape)
         with torch.cuda.device(self.device):
             self.stream.wait_stream(torch.cuda.current_stream())
             _lib.check(_lib.lib().sfseg_set_features(self._handle(), ps, pf),

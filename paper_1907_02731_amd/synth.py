@@ -25,7 +25,8 @@ import math
 
 import numpy as np
 
-__all__ = ["make_clip", "tiny_clip", "full_clip", "ragged_shapes", "random_vector"]
+__all__ = ["make_clip", "tiny_clip", "full_clip", "ragged_shapes", "random_vector",
+           "feature_channels"]
 
 
 def _rng(seed: int) -> np.random.Generator:
@@ -107,6 +108,20 @@ def full_clip(seed: int = 1, dtype=np.float32, T: int = 70, H: int = 480,
     """70 x 480 x 854 clip: affine-moving ellipse, 3 discs, noise 0.15."""
     return make_clip(T, H, W, seed=seed, n_blobs=3, noise_sigma=0.15,
                      motion="affine", dtype=dtype)
+
+
+def feature_channels(T: int, H: int, W: int, *, seed: int, n_blobs: int = 3,
+                     noise_sigma: float = 0.15, motion: str = "affine",
+                     dtype=np.float32) -> np.ndarray:
+    """Two pairwise feature channels (2, T, H, W) for the multi-channel form:
+    channel 0 is the clip itself (object, distractors, noise), channel 1 a
+    motion-like map of the same scene -- the moving object at 1.0 with the
+    same trajectory, no static distractors, light noise (sigma 0.05)."""
+    a = make_clip(T, H, W, seed=seed, n_blobs=n_blobs, noise_sigma=noise_sigma, motion=motion,
+                  dtype=dtype)
+    b = make_clip(T, H, W, seed=seed, n_blobs=n_blobs, noise_sigma=0.05, motion=motion,
+                  object_value=1.0, blob_value=0.0, dtype=dtype)
+    return np.stack([a, b])
 
 
 def ragged_shapes(n: int, seed: int = 3):
