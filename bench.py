@@ -35,21 +35,23 @@ ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 ALU_PEAK_PACKED_TFLOPS = 157.3  # vendor figure, packed FP32
 
 
-def flops_per_voxel(r_s: int, r_t: int) -> int:
-    """Algorithmic FLOPs of one step per voxel: three fields, each filtered
-    along y, x (2 r_s + 1 taps) and t (2 r_t + 1 taps) at 2 flop per tap;
-    3 to form the fields, 7 for the combine of Eq. (7), 4 for the two float64
-    reduction FMAs."""
-    return 3 * 2 * (2 * (2 * r_s + 1) + (2 * r_t + 1)) + 3 + 7 + 4
+def flops_per_voxel(r_s: int, r_t: int, nf: int = 1) -> int:
+    """Algorithmic FLOPs of one step per voxel: 1 + 2 nf fields (nf feature
+    channels), each filtered along y, x (2 r_s + 1 taps) and t (2 r_t + 1
+    taps) at 2 flop per tap; 1 + 2 nf to form the fields, 1 + 6 nf for the
+    combine of Eq. (7) (summed over channels, Eq. (9)), 4 for the two float64
+    reduction FMAs.  176 for one channel at r_s = 5, r_t = 2."""
+    nfld = 1 + 2 * nf
+    return nfld * 2 * (2 * (2 * r_s + 1) + (2 * r_t + 1)) + nfld + (1 + 6 * nf) + 4
 
 
 def roofline(kernel: str, voxels: float, seconds: float, storage: str, r_s: int, r_t: int,
-             traffic):
+             traffic, nf: int = 1):
     """Roofline entry of the step kernel: bound by VALU arithmetic (packed FP32
     being unavailable, 176 flop per 16 bytes is above the 9.8 flop/B balance),
     with the HBM view alongside."""
-    fl = flops_per_voxel(r_s, r_t) * voxels
-    by = BYTES_PER_VOXEL[storage] * voxels
+    fl = flops_per_voxel(r_s, r_t, nf) * voxels
+    by = (BYTES_PER_VOXEL[storage] + (nf - 1) * BYTES_PER_VOXEL[storage] // 4) * voxels
     tf = fl / seconds / 1e12
     gbs = by / seconds / 1e9
     out = {"bound": "alu", "kernel": kernel, "achieved": tf, "peak": ALU_PEAK_TFLOPS,
@@ -74,7 +76,7 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str, storage: str):
+def measured_traffic(workload: str, storage: str, nf: int = 1):
     """HBM bytes per step-kernel launch from the committed counter summary,
     if it was taken on the kernel sources as they are now (else None)."""
     try:
@@ -84,7 +86,8 @@ def measured_traffic(workload: str, storage: str):
         return None
     if t.get("kernel_source_hash") != kernel_source_hash():
         return None
-    entry = t.get("workloads", {}).get(f"{workload}/{storage}")
+    key = f"{workload}/{storage}" + ("" if nf == 1 else f"/nf{nf}")
+    entry = t.get("workloads", {}).get(key)
     return None if entry is None else entry.get("hbm_bytes_per_launch")
 BYTES_PER_VOXEL = {"f32": 16, "bf16": 8, "f16": 8}
 
@@ -122,20 +125,23 @@ def parse():
     ap.add_argument("--calibration-copy", action="store_true",
                     help="run plain torch copies of 4*T*H*W bytes first (to scale the HBM "
                          "byte counters of a profiling run)")
+    ap.add_argument("--features", type=int, default=1, choices=[1, 2],
+                    help="pairwise feature channels (2: the clip and a motion-like map, Eq. (9))")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=20,
                     help="oracle power-iteration steps timed for the CPU baseline")
     return ap.parse_args()
 
 
-def cpu_baseline(S, cfg_o, steps):
+def cpu_baseline(S, cfg_o, steps, Fs=None):
     from oracle import power_iteration
     from oracle.native import MatrixFree, num_threads
 
-    mf = MatrixFree(S, None, cfg_o)
+    # several feature channels: the matrix is the sum of the per-channel ones
+    mfs = [MatrixFree(S, None, cfg_o)] if Fs is None else [MatrixFree(S, F, cfg_o) for F in Fs]
     x0 = S.astype(np.float64).ravel()
     t0 = time.perf_counter()
-    power_iteration(mf.apply, x0, steps, 0.0)
+    power_iteration(lambda v: sum(m.apply(v) for m in mfs), x0, steps, 0.0)
     dt = time.perf_counter() - t0
     return {"value": S.size * steps / dt, "unit": "voxel-iterations/s", "cores": num_threads(),
             "kind": "oracle",
@@ -326,13 +332,22 @@ def main():
     import torch
 
     from paper_1907_02731_amd.solver import Solver
-    from paper_1907_02731_amd.synth import full_clip, tiny_clip
+    from paper_1907_02731_amd.synth import feature_channels, full_clip, tiny_clip
 
     T, H, W, r_t, r_s, s_t, s_s, seed = WORKLOADS[args.workload]
     S = full_clip(seed) if args.workload == "full" else tiny_clip(seed).astype(np.float32)
     assert S.shape == (T, H, W)
+    nf = args.features
+    Fs = None
+    if nf > 1:
+        if args.workload == "full":
+            Fs = feature_channels(T, H, W, seed=seed)
+        else:
+            Fs = feature_channels(T, H, W, seed=seed, n_blobs=2, noise_sigma=0.1, motion="drift")
+        S = Fs[0].copy()
     dev = torch.device("cuda:0")
     St = torch.from_numpy(S).to(dev)
+    Ft = None if Fs is None else torch.from_numpy(Fs).to(dev)
     out = torch.empty_like(St)
     if args.calibration_copy:
         for _ in range(3):
@@ -341,7 +356,7 @@ def main():
 
     kw = dict(r_t=r_t, r_s=r_s, sigma_t=s_t, sigma_s=s_s, alpha=args.alpha, p=args.p,
               storage=args.storage)
-    sol = Solver(St, **kw)
+    sol = Solver(St, Ft, **kw)
     plan_info = sol.autotune(steps=8) if args.autotune else None
     if args.shape >= 0 or args.chunks > 0:
         pl = sol.plan()
@@ -351,7 +366,7 @@ def main():
     max_iters, tol = (args.iters, 0.0) if args.iters > 0 else (args.max_iters, args.tol)
 
     def one_step():
-        sol.set_features(St)
+        sol.set_features(St, Ft)
         r = sol.iterate(max_iters=max_iters, tol=tol)
         sol.eigvec(out)
         return r, sol.timing()
@@ -388,8 +403,9 @@ def main():
         "config": {
             "workload": f"{args.workload}: one {T}x{H}x{W} clip, r_s={r_s}, r_t={r_t}, "
                         f"sigma_s={s_s}, sigma_t={s_t}, alpha={args.alpha}, p={args.p}, "
-                        f"power iteration from S to delta<{args.tol:g}",
-            "T": T, "H": H, "W": W, "tol": args.tol,
+                        f"power iteration from S to delta<{args.tol:g}"
+                        + (f", {nf} pairwise feature channels" if nf > 1 else ""),
+            "T": T, "H": H, "W": W, "tol": args.tol, "features": nf,
         },
         "iters_per_step": iters,
         "plan": sol.plan(),
@@ -399,7 +415,9 @@ def main():
         "lambda": last.lam,
         "time_to_converge_ms": elapsed * 1e3 / args.steps,
         "roofline": roofline("step_kernel (fused stencil + reductions)", N, avg_kernel_s,
-                             args.storage, r_s, r_t, measured_traffic(args.workload, args.storage)),
+                             args.storage, r_s, r_t,
+                             measured_traffic(args.workload, args.storage, nf),
+                             nf=nf),
     }
     if args.precision_report:
         line["precision"] = precision_report(S, St, kw, max(iters), out)
@@ -407,7 +425,8 @@ def main():
         from oracle import OracleConfig
         cfg_o = OracleConfig(r_t=r_t, r_s=r_s, sigma_t=s_t, sigma_s=s_s, alpha=args.alpha,
                              p=args.p)
-        line["cpu_baseline"] = cpu_baseline(S, cfg_o, args.cpu_steps)
+        line["cpu_baseline"] = cpu_baseline(S, cfg_o, args.cpu_steps if nf == 1 else
+                                            max(1, args.cpu_steps // nf), Fs)
     sol.close()
     print(json.dumps(line), flush=True)
 

@@ -104,3 +104,19 @@ def test_errors(clip):
     assert L.sfseg_create_mc(ctypes.byref(cfg16), s_.data_ptr(), f_.data_ptr(), 2, None,
                              ctypes.byref(out)) == _lib.SFSEG_ERR_UNSUPPORTED
     assert not out.value
+
+
+def test_full_size_sampled_rows():
+    """70 x 480 x 854, r_s = 5, r_t = 2, two channels: 20,000 sampled rows of
+    M x against the matrix-free FP64 oracle summed over channels."""
+    from oracle.native import MatrixFree
+    cfg = OracleConfig(r_t=2, r_s=5, sigma_t=1.0, sigma_s=2.0, alpha=1.0, p=0.2)
+    Fs = feature_channels(70, 480, 854, seed=1)
+    S = Fs[0]
+    r = np.random.Generator(np.random.PCG64(12))
+    x = r.random(S.shape).astype(np.float32)
+    rows = np.sort(r.choice(S.size, size=20000, replace=False))
+    with Solver(_t(S), _t(Fs), r_t=2, r_s=5, sigma_t=1.0, sigma_s=2.0, alpha=1.0, p=0.2) as sol:
+        y = _f64(sol.apply(_t(x))).ravel()
+    ref = sum(MatrixFree(S, F, cfg).apply_rows(x.astype(np.float64), rows) for F in Fs)
+    assert np.max(np.abs(y[rows] - ref)) <= 1e-5 * np.max(np.abs(ref))
