@@ -103,7 +103,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["batch", "warmstart"], default="full",
+    ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["batch", "warmstart", "segment"],
+                    default="full",
                     help="full: one 70x480x854 clip; tiny: 8x64x96; batch: 24 ragged clips "
                          "(frames 20-100, 240x427 / 360x640 / 480x854) in one batched solve, "
                          "timed against solving them one by one")
@@ -315,6 +316,118 @@ def bench_warmstart(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_segment(args):
+    """Algorithm 1 with the binarisation of Sec. 4.1 on the full-resolution
+    clip: 5 power iterations from S, sigmoid projection after iterations 3 and
+    4 (slope 10, threshold 0.5), hard threshold into a uint8 mask.  A step is
+    set features + the whole run, inputs in HBM.  The cost of one projection
+    and of the threshold is taken live from the library's HIP events by
+    running the same solve without them."""
+    import torch
+
+    from paper_1907_02731_amd.solver import Solver
+    from paper_1907_02731_amd.synth import full_clip
+
+    T, H, W, r_t, r_s, s_t, s_s, seed = WORKLOADS["full"]
+    iters, k0, slope, thr = 5, 3, 10.0, 0.5
+    S = full_clip(seed)
+    dev = torch.device("cuda:0")
+    St = torch.from_numpy(S).to(dev)
+    mask = torch.empty((T, H, W), dtype=torch.uint8, device=dev)
+    if args.calibration_copy:
+        cp = torch.empty_like(St)
+        for _ in range(3):
+            cp.copy_(St)
+        del cp
+    kw = dict(r_t=r_t, r_s=r_s, sigma_t=s_t, sigma_s=s_s, alpha=args.alpha, p=args.p,
+              storage=args.storage)
+    sol = Solver(St, **kw)
+
+    def one_step():
+        sol.set_features(St)
+        return sol.segment(iters=iters, project_from=k0, slope=slope, threshold=thr, out=mask)[0]
+
+    for _ in range(args.warmup):
+        one_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    recs = [one_step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    def lib_ms(**kw_seg):
+        out = []
+        for _ in range(5):
+            sol.segment(iters=iters, slope=slope, threshold=thr, **kw_seg)
+            out.append(sol.timing())
+        return (float(np.median([t["total_ms"] for t in out])),
+                float(np.median([t["loop_ms"] for t in out])))
+
+    _, plain_loop = lib_ms(project_from=iters, mask=False)
+    proj_total, _ = lib_ms(project_from=k0, mask=False)
+    plain_total, _ = lib_ms(project_from=iters, mask=False)
+    full_total, _ = lib_ms(project_from=k0, out=mask)
+    n_proj = iters - k0
+    step_s = plain_loop / 1e3 / iters
+    proj_s = (proj_total - plain_total) / 1e3 / n_proj
+    thr_s = (full_total - proj_total) / 1e3
+    N = T * H * W
+    # algorithmic bytes: the projection reads Y and writes P, the threshold
+    # reads Y and writes the uint8 mask; the max pass that each needs first
+    # (one more read of Y) is an implementation cost and counts against them
+    es = BYTES_PER_VOXEL[args.storage] // 4
+    proj_bytes = 2 * es * N
+    thr_bytes = (es + 1) * N
+    last = recs[-1]
+    line = {
+        "metric": "voxel-iterations/s (Algorithm 1 with binarisation, 5 iterations)",
+        "value": N * iters * args.steps / elapsed,
+        "unit": "voxel-iterations/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": args.storage, "data": "synthetic",
+        "config": {"workload": f"segment: one {T}x{H}x{W} clip, r_s={r_s}, r_t={r_t}, "
+                               f"sigma_s={s_s}, sigma_t={s_t}, alpha={args.alpha}, p={args.p}, "
+                               f"{iters} power iterations from S, sigmoid projection after "
+                               f"iterations {k0}..{iters - 1} (slope {slope:g}, threshold "
+                               f"{thr:g}), hard threshold into a uint8 mask",
+                   "T": T, "H": H, "W": W, "iters": iters, "project_from": k0,
+                   "slope": slope, "threshold": thr},
+        "lambda": last.lam, "delta": last.delta,
+        "mask_fraction": float(mask.float().mean().item()),
+        "roofline": roofline("step_kernel (fused stencil + reductions)", N, step_s,
+                             args.storage, r_s, r_t, measured_traffic("full", args.storage)),
+        "binarize": {
+            "project_us": proj_s * 1e6, "project_bytes": proj_bytes,
+            "project_GBps": proj_bytes / proj_s / 1e9,
+            "project_frac_hbm": proj_bytes / proj_s / 1e9 / HBM_PEAK_GBS,
+            "threshold_us": thr_s * 1e6, "threshold_bytes": thr_bytes,
+            "threshold_GBps": thr_bytes / thr_s / 1e9,
+            "threshold_frac_hbm": thr_bytes / thr_s / 1e9 / HBM_PEAK_GBS,
+            "note": "max + projection + finish launches and max + threshold launches, each "
+                    "the difference of library-timed solves with and without them (medians "
+                    "of 5); bytes are algorithmic (Y read once, P or the mask written)",
+        },
+    }
+    if not args.no_cpu_baseline:
+        from oracle import OracleConfig
+        from oracle.binarize_oracle import segment
+        from oracle.native import MatrixFree, num_threads
+        cfg_o = OracleConfig(r_t=r_t, r_s=r_s, sigma_t=s_t, sigma_s=s_s, alpha=args.alpha, p=args.p)
+        mf = MatrixFree(S, None, cfg_o)
+        c0 = time.perf_counter()
+        segment(mf.apply, S.astype(np.float64).ravel(), iters, k0, slope, thr)
+        dt = time.perf_counter() - c0
+        line["cpu_baseline"] = {
+            "value": N * iters / dt, "unit": "voxel-iterations/s", "cores": num_threads(),
+            "kind": "oracle",
+            "sample": f"the whole FP64 Algorithm 1 ({iters} iterations, projections, threshold) "
+                      f"of the matrix-free oracle on the {T}x{H}x{W} clip ({dt:.1f} s)"}
+    sol.close()
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -327,6 +440,9 @@ def main():
         return
     if args.workload == "warmstart":
         bench_warmstart(args)
+        return
+    if args.workload == "segment":
+        bench_segment(args)
         return
 
     import torch

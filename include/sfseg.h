@@ -166,6 +166,56 @@ int sfseg_eigvec(sfseg_ctx *ctx, float *out);
  * first.  Does not disturb the iteration state.  Blocks until done. */
 int sfseg_apply(sfseg_ctx *ctx, const float *x, float *y);
 
+/* ---- Binarisation (Sec. 4.1; Alg. 1, step 3) ---------------------------
+ * Algorithm 1 projects the normalised solution through a sigmoid after each
+ * iteration once a few unconstrained iterations have run, starts the next
+ * iteration from the projection, and hard-thresholds the solution after the
+ * last one.  The paper leaves the sigmoid's slope, centre, start iteration
+ * and scale open; this library reads them as:
+ *     z_i  = x_i / max_j x_j                         (scale-free, in [0, 1] for x >= 0)
+ *     P_i  = 1 / (1 + exp(-slope (z_i - threshold)))   projection
+ *     mask_i = [x_i > threshold * max_j x_j]         hard threshold (strict)
+ * The projection is computed in float32 from the stored iterate; the
+ * threshold compares the stored values exactly (float64 product of two
+ * float32 numbers).  The fixed point is no longer an eigenvector of M. */
+typedef struct sfseg_binarize {
+    int32_t iters;        /* outer iterations N_i (power steps), >= 1 */
+    int32_t project_from; /* project after iterations k with project_from <= k < iters
+                             (>= iters: never; must be >= 1) */
+    float slope;          /* sigmoid slope, finite and > 0 */
+    float threshold;      /* sigmoid centre and hard threshold (relative to the max), finite */
+} sfseg_binarize;
+
+/* Defaults: iters = 5 (the paper's experiments), project_from = 3, slope = 10,
+ * threshold = 0.5.  Host only. */
+void sfseg_binarize_default(sfseg_binarize *b);
+
+/* Replace the current iterate x by the sigmoid projection P(x) above and
+ * renormalise (float64 fixed-order norm), so that sfseg_eigvec then returns
+ * P / ||P||.  Voxels outside the picture are untouched.  Blocks until done.
+ * Errors: SFSEG_ERR_INVALID_ARG for a non-positive or non-finite slope or a
+ * non-finite threshold; SFSEG_ERR_STATE before a successful iterate;
+ * SFSEG_ERR_ZERO_NORM when no entry of x is positive; SFSEG_ERR_NONFINITE for
+ * a non-finite maximum. */
+int sfseg_project(sfseg_ctx *ctx, float slope, float threshold);
+
+/* Hard threshold of the current iterate into mask (device uint8, T*H*W, owned
+ * by the caller): 1 where x_i > threshold * max_j x_j, else 0.  Ordered on the
+ * stream; does not block.  SFSEG_ERR_STATE before a successful iterate. */
+int sfseg_threshold(sfseg_ctx *ctx, float threshold, uint8_t *mask);
+
+/* Algorithm 1 with binarisation: x <- x0 / ||x0|| (x0 == NULL: S); for
+ * k = 1 .. b->iters one power step (Eqs. (4), (8)), then the projection when
+ * b->project_from <= k < b->iters; finally the hard threshold of the last
+ * power iterate into mask (device uint8, T*H*W; may be NULL to skip it).  No
+ * tolerance: exactly b->iters steps run.  *res (host, may be NULL) receives
+ * iters, converged = 0, and delta / lambda of the last step (measured against
+ * its unit input, the projected vector when the step before was projected).
+ * Leaves the last power iterate as the current iterate.  Blocks until done.
+ * Errors as sfseg_power_iterate and sfseg_project. */
+int sfseg_segment(sfseg_ctx *ctx, const float *x0, const sfseg_binarize *b, uint8_t *mask,
+                  sfseg_result *res);
+
 /* Current work plan of the step kernel.  Host only. */
 int sfseg_get_plan(const sfseg_ctx *ctx, sfseg_plan *out);
 

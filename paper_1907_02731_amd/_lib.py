@@ -45,6 +45,11 @@ class Timing(ctypes.Structure):
                 ("launches", ctypes.c_int32)]
 
 
+class Binarize(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("project_from", ctypes.c_int32),
+                ("slope", ctypes.c_float), ("threshold", ctypes.c_float)]
+
+
 class Plan(ctypes.Structure):
     _fields_ = [("shape", ctypes.c_int32), ("chunks", ctypes.c_int32),
                 ("blocks", ctypes.c_int32), ("threads", ctypes.c_int32)]
@@ -89,6 +94,15 @@ def lib():
     L.sfseg_eigvec.restype = ctypes.c_int
     L.sfseg_apply.argtypes = [P, P, P]
     L.sfseg_apply.restype = ctypes.c_int
+    pbin = ctypes.POINTER(Binarize)
+    L.sfseg_binarize_default.argtypes = [pbin]
+    L.sfseg_binarize_default.restype = None
+    L.sfseg_project.argtypes = [P, ctypes.c_float, ctypes.c_float]
+    L.sfseg_project.restype = ctypes.c_int
+    L.sfseg_threshold.argtypes = [P, ctypes.c_float, P]
+    L.sfseg_threshold.restype = ctypes.c_int
+    L.sfseg_segment.argtypes = [P, P, pbin, P, ctypes.POINTER(Result)]
+    L.sfseg_segment.restype = ctypes.c_int
     L.sfseg_get_plan.argtypes = [P, ctypes.POINTER(Plan)]
     L.sfseg_get_plan.restype = ctypes.c_int
     L.sfseg_set_plan.argtypes = [P, ctypes.c_int32, ctypes.c_int32]

@@ -45,6 +45,8 @@ struct sfseg_ctx;
 
 namespace sfseg_host {
 int batch_get_plan(const sfseg_ctx* ctx, sfseg_plan* out);
+// Enqueue `count` single steps, the first from buf[first_buf & 1].
+int launch_steps(sfseg_ctx* ctx, int first_buf, int count);
 int batch_set_plan(sfseg_ctx* ctx, int32_t shape, int32_t chunks);
 }  // namespace sfseg_host
 

@@ -143,6 +143,52 @@ class Solver:
             torch.cuda.current_stream().wait_stream(self.stream)
         return out
 
+    # -- binarisation (Sec. 4.1) ----------------------------------------------
+    def _mask_out(self, out: Optional[torch.Tensor]) -> torch.Tensor:
+        if out is None:
+            with torch.cuda.stream(self.stream):
+                return torch.empty(self.shape, dtype=torch.uint8, device=self.device)
+        if (not isinstance(out, torch.Tensor) or out.device.type != "cuda"
+                or out.dtype != torch.uint8 or not out.is_contiguous()
+                or tuple(out.shape) != tuple(self.shape)):
+            raise TypeError(f"mask must be a contiguous uint8 CUDA tensor of shape {self.shape}")
+        self.stream.wait_stream(torch.cuda.current_stream())
+        return out
+
+    def project(self, slope: float = 10.0, threshold: float = 0.5) -> None:
+        """Replace the current iterate by its sigmoid projection (sfseg_project)."""
+        with torch.cuda.device(self.device):
+            self.stream.wait_stream(torch.cuda.current_stream())
+            _lib.check(_lib.lib().sfseg_project(self._handle(), float(slope), float(threshold)),
+                       "sfseg_project")
+
+    def threshold(self, threshold: float = 0.5,
+                  out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """Hard threshold of the current iterate as a uint8 (T, H, W) mask."""
+        with torch.cuda.device(self.device):
+            out = self._mask_out(out)
+            _lib.check(_lib.lib().sfseg_threshold(self._handle(), float(threshold),
+                                                  out.data_ptr()), "sfseg_threshold")
+            torch.cuda.current_stream().wait_stream(self.stream)
+        return out
+
+    def segment(self, x0: Optional[torch.Tensor] = None, iters: int = 5, project_from: int = 3,
+                slope: float = 10.0, threshold: float = 0.5, mask: bool = True,
+                out: Optional[torch.Tensor] = None):
+        """Algorithm 1 with the Sec. 4.1 binarisation (sfseg_segment).
+        Returns (IterResult, uint8 mask or None)."""
+        px = _dev_ptr(x0, "x0", self.shape)
+        b = _lib.Binarize(int(iters), int(project_from), float(slope), float(threshold))
+        res = _lib.Result()
+        with torch.cuda.device(self.device):
+            m = self._mask_out(out) if mask else None
+            self.stream.wait_stream(torch.cuda.current_stream())
+            _lib.check(_lib.lib().sfseg_segment(self._handle(), px, ctypes.byref(b),
+                                                None if m is None else m.data_ptr(),
+                                                ctypes.byref(res)), "sfseg_segment")
+            torch.cuda.current_stream().wait_stream(self.stream)
+        return IterResult(int(res.iters), bool(res.converged), float(res.delta), float(res.lam)), m
+
     def plan(self) -> dict:
         pl = _lib.Plan()
         _lib.check(_lib.lib().sfseg_get_plan(self._handle(), ctypes.byref(pl)), "sfseg_get_plan")

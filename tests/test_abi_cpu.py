@@ -43,6 +43,7 @@ def test_struct_layout_matches_header():
     assert ctypes.sizeof(_lib.Config) == 56
     assert ctypes.sizeof(_lib.Result) == 24
     assert ctypes.sizeof(_lib.Timing) == 32
+    assert ctypes.sizeof(_lib.Binarize) == 16
 
 
 def test_config_default_and_validate():
@@ -101,6 +102,14 @@ def test_null_arguments_rejected():
         _lib.SFSEG_ERR_INVALID_ARG
     assert L.sfseg_set_features(None, ctypes.c_void_p(1), None) == _lib.SFSEG_ERR_INVALID_ARG
     assert L.sfseg_last_timing(None, None) == _lib.SFSEG_ERR_INVALID_ARG
+    b = _lib.Binarize()
+    L.sfseg_binarize_default(ctypes.byref(b))
+    assert (b.iters, b.project_from, b.slope, b.threshold) == (5, 3, 10.0, 0.5)
+    assert L.sfseg_project(None, 10.0, 0.5) == _lib.SFSEG_ERR_INVALID_ARG
+    assert L.sfseg_threshold(None, 0.5, ctypes.c_void_p(1)) == _lib.SFSEG_ERR_INVALID_ARG
+    assert L.sfseg_segment(None, None, ctypes.byref(b), None, None) == \
+        _lib.SFSEG_ERR_INVALID_ARG
+    L.sfseg_binarize_default(None)  # NULL-safe
     L.sfseg_destroy(None)  # NULL-safe
 
 
