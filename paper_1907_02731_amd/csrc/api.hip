@@ -104,7 +104,7 @@ void sfseg_destroy(sfseg_ctx* ctx) {
         if (e) (void)hipEventDestroy(e);
     void* dev[] = {ctx->w, ctx->f, ctx->s0, ctx->buf[0], ctx->buf[1], ctx->apply_in,
                    ctx->apply_out, ctx->st, ctx->st_apply, ctx->d_bad, ctx->partials,
-                   ctx->items};
+                   ctx->step_part, ctx->items};
     for (void* p : dev)
         if (p) (void)hipFree(p);
     if (ctx->h_st) (void)hipHostFree(ctx->h_st);
@@ -195,15 +195,23 @@ int install_plan(sfseg_ctx* ctx, int shape, int chunks) {
         HIP_TRY(hipMalloc((void**)&ctx->partials, sizeof(double) * 2 * need));
         ctx->partial_slots = need;
     }
+    if (grid > ctx->step_part_slots) {
+        if (ctx->step_part) HIP_TRY(hipFree(ctx->step_part));
+        ctx->step_part = nullptr;
+        HIP_TRY(hipMalloc((void**)&ctx->step_part, sizeof(double) * 4 * grid));
+        ctx->step_part_slots = grid;
+    }
     HIP_TRY(hipMemcpyAsync(ctx->items, items.data(), sizeof(int4) * items.size(),
                            hipMemcpyHostToDevice, ctx->stream));
     HIP_TRY(hipStreamSynchronize(ctx->stream));
     ctx->shape = shape;
     ctx->chunks = chunks;
     ctx->step_grid = grid;
-    for (auto& p : ctx->params) {
+    for (int b = 0; b < 2; ++b) {
+        StepParams& p = ctx->params[b];
         p.items = ctx->items;
-        p.partials = ctx->partials;
+        p.part_in = ctx->step_part + 2 * (size_t)ctx->step_part_slots * b;
+        p.part_out = ctx->step_part + 2 * (size_t)ctx->step_part_slots * (1 - b);
     }
     if (ctx->graph) {
         (void)hipGraphExecDestroy(ctx->graph);
@@ -253,8 +261,8 @@ int setup(sfseg_ctx* ctx, const float* S, const float* F) {
     HIP_TRY(hipMalloc(&ctx->s0, bytes));
     HIP_TRY(hipMalloc(&ctx->buf[0], bytes));
     HIP_TRY(hipMalloc(&ctx->buf[1], bytes));
-    HIP_TRY(hipMalloc((void**)&ctx->st, sizeof(DevState)));
-    HIP_TRY(hipMalloc((void**)&ctx->st_apply, sizeof(DevState)));
+    HIP_TRY(hipMalloc((void**)&ctx->st, 2 * sizeof(DevState)));
+    HIP_TRY(hipMalloc((void**)&ctx->st_apply, 2 * sizeof(DevState)));
     HIP_TRY(hipMalloc((void**)&ctx->d_bad, sizeof(int32_t)));
     HIP_TRY(hipHostMalloc((void**)&ctx->h_st, 3 * sizeof(DevState), hipHostMallocDefault));
     HIP_TRY(hipHostMalloc((void**)&ctx->h_bad, sizeof(int32_t), hipHostMallocDefault));
@@ -263,8 +271,8 @@ int setup(sfseg_ctx* ctx, const float* S, const float* F) {
     void* vols[] = {ctx->w, ctx->s0, ctx->buf[0], ctx->buf[1]};
     for (void* v : vols) HIP_TRY(hipMemsetAsync(v, 0, bytes, ctx->stream));
     HIP_TRY(hipMemsetAsync(ctx->f, 0, bytes * ctx->nf, ctx->stream));
-    HIP_TRY(hipMemsetAsync(ctx->st, 0, sizeof(DevState), ctx->stream));
-    HIP_TRY(hipMemsetAsync(ctx->st_apply, 0, sizeof(DevState), ctx->stream));
+    HIP_TRY(hipMemsetAsync(ctx->st, 0, 2 * sizeof(DevState), ctx->stream));
+    HIP_TRY(hipMemsetAsync(ctx->st_apply, 0, 2 * sizeof(DevState), ctx->stream));
 
     for (int b = 0; b < 2; ++b) {
         StepParams& p = ctx->params[b];
@@ -273,7 +281,8 @@ int setup(sfseg_ctx* ctx, const float* S, const float* F) {
         p.y = ctx->buf[1 - b];
         p.w = ctx->w;
         p.f = ctx->f;
-        p.st = ctx->st;
+        p.st_in = ctx->st + b;
+        p.st_out = ctx->st + (1 - b);
         p.T = c.T;
         p.Wp = L.Wp;
         p.PT = L.PT;
@@ -330,11 +339,22 @@ int launch_steps(sfseg_ctx* ctx, int first_buf, int count) {
     return SFSEG_OK;
 }
 
+int launch_finish(sfseg_ctx* ctx, int slot) {
+    HIP_TRY(sfseg::launch_step_finish(ctx->st, slot & 1,
+                                      ctx->step_part + 2 * (size_t)ctx->step_part_slots * (slot & 1),
+                                      ctx->step_grid, ctx->stream));
+    return SFSEG_OK;
+}
+
+// kChunk steps from buf[0] (kChunk is even, so they end in buf[0]) and the
+// fold of the last one.
+static_assert(kChunk % 2 == 0, "a captured chunk must end in buf[0]");
 int ensure_graph(sfseg_ctx* ctx) {
     if (ctx->graph) return SFSEG_OK;
     hipGraph_t g = nullptr;
     HIP_TRY(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
     int rc = launch_steps(ctx, 0, kChunk);
+    if (rc == SFSEG_OK) rc = launch_finish(ctx, kChunk & 1);
     hipError_t e = hipStreamEndCapture(ctx->stream, &g);
     if (rc != SFSEG_OK) {
         if (g) (void)hipGraphDestroy(g);
@@ -429,6 +449,7 @@ int sfseg_power_iterate(sfseg_ctx* ctx, const float* x0, int32_t max_iters, doub
             } else {
                 const int cnt = remaining < kChunk ? remaining : kChunk;
                 int rc = launch_steps(ctx, launched & 1, cnt);
+                if (rc == SFSEG_OK) rc = launch_finish(ctx, (launched + cnt) & 1);
                 if (rc != SFSEG_OK) return rc;
                 launched += cnt;
             }
@@ -507,13 +528,14 @@ int sfseg_apply(sfseg_ctx* ctx, const float* x, float* y) {
     h.max_iters = 1;
     *ctx->h_st = h;
     HIP_TRY(hipMemcpyAsync(ctx->st_apply, ctx->h_st, sizeof(DevState), hipMemcpyHostToDevice,
-                           ctx->stream));
+                           ctx->stream));  // slot 0: nothing pending
     HIP_TRY(sfseg::launch_to_storage(ctx->cfg.storage, x, ctx->apply_in, ctx->L, ctx->ew_grid,
                                      ctx->stream));
     StepParams p = ctx->params[0];
     p.x = ctx->apply_in;
     p.y = ctx->apply_out;
-    p.st = ctx->st_apply;
+    p.st_in = ctx->st_apply;
+    p.st_out = ctx->st_apply + 1;
     HIP_TRY(sfseg::launch_step(ctx->cfg.storage, sfseg::kernel_shape(ctx->shape, ctx->nf),
                                ctx->cfg.r_s, ctx->cfg.r_t, p,
                                ctx->step_grid, ctx->stream));

@@ -173,8 +173,10 @@ __global__ __launch_bounds__(kNT) void project_kernel(TS* __restrict__ y, Layout
 }
 
 // One block: the fixed-order float64 sum of the projection's block sums, then
-// s = 1 / ||P||, c = s * gain; a maximum that is not positive or not finite
-// stops the iteration with SFSEG_ERR_ZERO_NORM or SFSEG_ERR_NONFINITE.
+// s = 1 / ||P||, c = s * gain in both state slots st[0], st[1] (the next step
+// reads the slot of the buffer that holds P); a maximum that is not positive
+// or not finite stops the iteration with SFSEG_ERR_ZERO_NORM or
+// SFSEG_ERR_NONFINITE.
 __global__ __launch_bounds__(kNT) void project_finish(DevState* st, const double* partials,
                                                       uint32_t nb, int skip_if_done) {
     if (skip_if_done && st->done) return;
@@ -183,15 +185,18 @@ __global__ __launch_bounds__(kNT) void project_finish(DevState* st, const double
     const float m = global_max(partials, nb, red);
     const double tss = fixed_order_sum<kNT>(partials, nb, 1, fin);
     if (threadIdx.x == 0) {
+        DevState s = st[0];
         const double n = sqrt(tss);
         if (!(isfinite(m) && m > 0.f) || !(n > 0.0) || !isfinite(n)) {
-            st->status = isfinite(m) ? SFSEG_ERR_ZERO_NORM : SFSEG_ERR_NONFINITE;
-            st->done = 1;
+            s.status = isfinite(m) ? SFSEG_ERR_ZERO_NORM : SFSEG_ERR_NONFINITE;
+            s.done = 1;
         } else {
-            st->status = SFSEG_OK;
-            st->s = 1.0 / n;
-            st->c = (float)(st->s * st->gain);
+            s.status = SFSEG_OK;
+            s.s = 1.0 / n;
+            s.c = (float)(s.s * s.gain);
         }
+        st[0] = s;
+        st[1] = s;
     }
 }
 
@@ -384,11 +389,16 @@ int sfseg_segment(sfseg_ctx* ctx, const float* x0, const sfseg_binarize* b, uint
     for (int k = 1; k <= b->iters; ++k) {
         rc = launch_steps(ctx, (k - 1) & 1, 1);
         if (rc != SFSEG_OK) return rc;
-        if (b->project_from <= k && k < b->iters)
+        if (b->project_from <= k && k < b->iters) {
+            rc = launch_finish(ctx, k & 1);  // the projection needs the step's norm
+            if (rc != SFSEG_OK) return rc;
             HIP_TRY(sfseg::launch_project(ctx->cfg.storage, ctx->buf[k & 1], ctx->L, ctx->st,
                                           ctx->partials, b->slope, b->threshold, 1, grid,
                                           ctx->stream));
+        }
     }
+    rc = launch_finish(ctx, b->iters & 1);
+    if (rc != SFSEG_OK) return rc;
     if (mask)
         HIP_TRY(sfseg::launch_threshold(ctx->cfg.storage, ctx->buf[b->iters & 1], ctx->L, ctx->st,
                                         ctx->partials, b->threshold, mask, grid, ctx->stream));

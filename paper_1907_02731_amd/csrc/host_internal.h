@@ -47,6 +47,9 @@ namespace sfseg_host {
 int batch_get_plan(const sfseg_ctx* ctx, sfseg_plan* out);
 // Enqueue `count` single steps, the first from buf[first_buf & 1].
 int launch_steps(sfseg_ctx* ctx, int first_buf, int count);
+// Enqueue the one-block fold that completes the state of buf[slot] (the last
+// step's output) and makes slot 0 current.
+int launch_finish(sfseg_ctx* ctx, int slot);
 int batch_set_plan(sfseg_ctx* ctx, int32_t shape, int32_t chunks);
 }  // namespace sfseg_host
 
@@ -61,12 +64,15 @@ struct sfseg_ctx {
     void* buf[2] = {nullptr, nullptr};
     void* apply_in = nullptr;
     void* apply_out = nullptr;
-    sfseg::DevState* st = nullptr;        // iteration state
-    sfseg::DevState* st_apply = nullptr;  // state used by sfseg_apply
+    sfseg::DevState* st = nullptr;        // iteration state, one slot per iterate buffer
+                                          // (slot 0 is current after every finish)
+    sfseg::DevState* st_apply = nullptr;  // the two slots used by sfseg_apply
     sfseg::DevState* h_st = nullptr;      // pinned host copies: [0] final, [1..2] per-chunk
     int32_t* d_bad = nullptr;
     int32_t* h_bad = nullptr;
-    double* partials = nullptr;
+    double* partials = nullptr;   // element-wise kernels' block sums
+    double* step_part = nullptr;  // step partial sums: set i belongs to the step that wrote buf[i]
+    int step_part_slots = 0;      // blocks each set holds
     int4* items = nullptr;  // step-kernel work items, one per block
     size_t items_cap = 0;   // capacity of `items` in entries
     sfseg::Layout L{};

@@ -8,13 +8,21 @@
 
 namespace sfseg {
 
-// Iteration state kept in device memory.  The fused step kernel reads it at
-// launch and its last block writes the next values, so a chain of step
-// launches (or a captured graph of them) runs without host round trips.
+// Iteration state kept in device memory, so a chain of step launches (or a
+// captured graph of them) runs without host round trips.
 //
 // The iterate is held unnormalised: buffer Y_k with x_k = s * Y_k, where
 // s = 1 / ||Y_k|| is computed in float64 from the stored values.  A step
 // writes Y_{k+1} = c * M Y_k with the float32 multiplier c = fl32(s * gain).
+//
+// Single clips keep two slots, one per iterate buffer.  A step launch reads
+// the slot of its input buffer and writes the slot of its output buffer; its
+// blocks leave only their float64 partial sums.  The next launch (or a
+// one-block finish launch) folds those sums into the state: every one of its
+// blocks adds them in the same fixed order, so all take the same scale and
+// the same stop decision, and block 0 records the result.  No block waits on
+// another inside a launch, so no launch needs a device-wide memory fence.
+// Batched clips keep one slot each and fold in the launch's last block.
 struct DevState {
     double s;       // 1 / ||Y_k||
     double lambda;  // x_{k-1}^T M x_{k-1} of the last step
@@ -27,8 +35,9 @@ struct DevState {
     int32_t done;       // 1: later step launches return at once
     int32_t status;     // SFSEG_OK or the error that stopped the iteration
     int32_t converged;  // delta < tol reached
-    uint32_t ticket;    // arrival counter of the current launch (reset by the last block)
-    int32_t pad;
+    uint32_t ticket;    // arrival counter of a launch that folds in its last block
+    int32_t pending;    // 1: the partial sums of the step that wrote this slot's buffer
+                        // are not folded in yet (single clips)
 };
 
 // Zero-padded storage layout of every internal volume: frames of Hp x Wp
@@ -50,8 +59,10 @@ struct StepParams {
     const void* w;  // S^p
     const void* f;  // F
     void* y;        // Y_{k+1}
-    DevState* st;
-    double* partials;    // 2 doubles per block
+    const DevState* st_in;  // state of x
+    DevState* st_out;       // state of y (written by block 0)
+    const double* part_in;  // partial sums of the step that wrote x (2 per block)
+    double* part_out;       // this launch's partial sums (2 per block)
     const int4* items;   // per logical block: tile origin x, y (picture coords), frames [z, w)
     int32_t T, Wp, PT, PL;
     int64_t frame;
@@ -99,6 +110,11 @@ constexpr int step_threads(int shape) { return shape == 0 ? 256 : 512; }
 
 hipError_t launch_step(int dtype, int shape, int rs, int rt, const StepParams& p, int grid,
                        hipStream_t stream);
+// One block: fold the partial sums `part` (2 per block of a step launch of
+// `nblocks` blocks) into slot st2[slot] if they are pending, then copy the
+// state into both slots st2[0] and st2[1].
+hipError_t launch_step_finish(DevState* st2, int slot, const double* part, int nblocks,
+                              hipStream_t stream);
 hipError_t step_max_blocks_per_cu(int dtype, int shape, int rs, int rt, int* blocks);
 hipError_t launch_batch_step(int dtype, int shape, int rs, int rt, const BatchParams& p, int grid,
                              hipStream_t stream);

@@ -30,10 +30,13 @@
 // and along x back into registers, and pushes the result into a register ring
 // of 2 r_t + 1 frames; once the ring holds frames t - r_t .. t + r_t it filters
 // along t, combines, stores frame t and accumulates sum(y^2) and sum(y * Y_k)
-// in float64 on the stored values.  The
-// block's partial sums go to memory; the last block to finish reduces all
-// partials in a fixed order and advances the iteration state (norm, Rayleigh
-// quotient, change, convergence flag), so results are bit-reproducible.
+// in float64 on the stored values.  The block's partial sums go to memory.
+// The next launch's blocks each add all of them in a fixed order and advance
+// the iteration state (norm, Rayleigh quotient, change, convergence flag) in
+// registers -- identical bits in every block -- before they start, so
+// results are bit-reproducible and no block ever waits on another: a
+// last-block ticket would need an agent-scope release fence in every block,
+// which on this multi-XCD part writes back the XCD's L2 each time.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -241,37 +244,109 @@ __device__ bool block_partials_and_ticket(double a, double b, double* partials, 
     return last;
 }
 
-// Advance the iteration state after a step; run by thread 0 of the last block.
+// Advance the iteration state after a step.
 //   syy = sum(y_i^2), syx = sum(y_i * Y_k,i) over the stored values, where
 //   y = c * M Y_k and x_k = s * Y_k.  Then
 //   M x_k = (s / c) y            =>  lambda = x_k^T M x_k = s^2 syx / c
 //   x_{k+1} = y / ||y||          =>  x_{k+1} . x_k = s syx / ||y||
 //   delta = ||x_{k+1} - x_k|| = sqrt(2 - 2 x_{k+1} . x_k)   (both unit vectors)
-__device__ inline void advance_state(DevState* st, double syy, double syx) {
+__device__ inline void advance_values(DevState& st, double syy, double syx) {
     const double n = sqrt(syy);
-    const double s = st->s;
-    const double c = (double)st->c;
-    st->k += 1;
+    const double s = st.s;
+    const double c = (double)st.c;
+    st.k += 1;
     if (!isfinite(n) || !isfinite(syx)) {
-        st->status = SFSEG_ERR_NONFINITE;
-        st->done = 1;
+        st.status = SFSEG_ERR_NONFINITE;
+        st.done = 1;
         return;
     }
     if (!(n > 0.0)) {
-        st->status = SFSEG_ERR_ZERO_NORM;
-        st->done = 1;
+        st.status = SFSEG_ERR_ZERO_NORM;
+        st.done = 1;
         return;
     }
-    st->lambda = s * s * syx / c;
+    st.lambda = s * s * syx / c;
     const double cosv = s * syx / n;
-    st->delta = sqrt(fmax(0.0, 2.0 - 2.0 * cosv));
-    st->s = 1.0 / n;
-    st->c = (float)(st->s * st->gain);
-    if (st->delta < st->tol) {
-        st->converged = 1;
-        st->done = 1;
+    st.delta = sqrt(fmax(0.0, 2.0 - 2.0 * cosv));
+    st.s = 1.0 / n;
+    st.c = (float)(st.s * st.gain);
+    if (st.delta < st.tol) {
+        st.converged = 1;
+        st.done = 1;
     }
-    if (st->k >= st->max_iters) st->done = 1;
+    if (st.k >= st.max_iters) st.done = 1;
+}
+
+// The same on a state in memory; run by thread 0 of the last block.
+__device__ inline void advance_state(DevState* st, double syy, double syx) {
+    advance_values(*st, syy, syx);
+}
+
+// Block-wide sums of a and b (each wave in a fixed butterfly, then the waves
+// in order) written to part[2*slot], part[2*slot+1].
+template <int NT>
+__device__ void block_partials(double a, double b, double* part, int slot) {
+    __shared__ double red[2][NT / 64];
+    a = wave_sum(a);
+    b = wave_sum(b);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) {
+        red[0][wid] = a;
+        red[1][wid] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double sa = 0.0, sb = 0.0;
+#pragma unroll
+        for (int i = 0; i < NT / 64; ++i) {
+            sa += red[0][i];
+            sb += red[1][i];
+        }
+        agent_store(part + 2 * slot, sa);
+        agent_store(part + 2 * slot + 1, sb);
+    }
+}
+
+// Fixed-order sums of the nblocks partial pairs of a step launch, the same
+// bits in every block of any size >= 256: lanes 0..255 add blocks i, i + 256,
+// ... in turn, each of the first four waves reduces its lanes, and the four
+// wave sums are added in order.  Every thread gets both sums.
+template <int NT>
+__device__ void fold_partials(const double* part, int nblocks, double (*red)[4], double& a,
+                              double& b) {
+    static_assert(NT >= 256, "the fold needs four full waves");
+    double sa = 0.0, sb = 0.0;
+    if (threadIdx.x < 256) {
+        for (int i = threadIdx.x; i < nblocks; i += 256) {
+            sa += agent_load(part + 2 * i);
+            sb += agent_load(part + 2 * i + 1);
+        }
+    }
+    sa = wave_sum(sa);
+    sb = wave_sum(sb);
+    if (threadIdx.x < 256 && (threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = sa;
+        red[1][threadIdx.x >> 6] = sb;
+    }
+    __syncthreads();
+    a = ((red[0][0] + red[0][1]) + red[0][2]) + red[0][3];
+    b = ((red[1][0] + red[1][1]) + red[1][2]) + red[1][3];
+    __syncthreads();
+}
+
+// The state of a step launch's input: the slot as written, with the partial
+// sums of the step that wrote the input folded in if they are pending.
+template <int NT>
+__device__ DevState state_of_input(const DevState* slot, const double* part, int nblocks,
+                                   double (*red)[4]) {
+    DevState s = *slot;
+    if (s.pending) {
+        double syy, syx;
+        fold_partials<NT>(part, nblocks, red, syy, syx);
+        s.pending = 0;
+        advance_values(s, syy, syx);
+    }
+    return s;
 }
 
 // XCD-aware block order: hardware deals block b to XCD b % 8; give XCD x the
@@ -645,11 +720,19 @@ __global__ __launch_bounds__(SH::NT, (Geom<TS, RS, RT, SH>::MINW)) void step_ker
     using G = Geom<TS, RS, RT, SH>;
     constexpr int NT = G::NT, NR = G::NR;
     __shared__ StepLds<TS, RS, RT, SH> lds;
+    __shared__ double fold_red[2][4];
 
-    DevState* st = p.st;
-    if (st->done) return;
+    // Fold the previous step's partial sums (every block, same bits), record
+    // the state for this launch's output, and stop if the iteration has.
+    const DevState s = state_of_input<NT>(p.st_in, p.part_in, gridDim.x, fold_red);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        DevState o = s;
+        o.pending = s.done ? 0 : 1;
+        *p.st_out = o;
+    }
+    if (s.done) return;
 
-    const float c = st->c;
+    const float c = s.c;
     float gs[RS + 1];
 #pragma unroll
     for (int d = 0; d <= RS; ++d) gs[d] = p.gs[d];
@@ -663,15 +746,7 @@ __global__ __launch_bounds__(SH::NT, (Geom<TS, RS, RT, SH>::MINW)) void step_ker
     run_item<TS, RS, RT, SH>((const TS*)p.x, (const TS*)p.w, (const TS*)p.f, p.fstride,
                              (TS*)p.y, p.T, p.Wp, p.PT, p.PL, p.frame, item.x, item.y, item.z,
                              item.w, gs, gt, p.alpha, lds, syy, syx);
-
-    if (block_partials_and_ticket<NT>(syy, syx, p.partials, lb, &st->ticket, (uint32_t)gridDim.x)) {
-        const double tyy = fixed_order_sum<NT>(p.partials, gridDim.x, 0, lds.fin);
-        const double tyx = fixed_order_sum<NT>(p.partials, gridDim.x, 1, lds.fin);
-        if (threadIdx.x == 0) {
-            advance_state(st, tyy, tyx);
-            __hip_atomic_store(&st->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-    }
+    block_partials<NT>(syy, syx, p.part_out, lb);
 }
 
 // ---------------------------------------------------------------------------
