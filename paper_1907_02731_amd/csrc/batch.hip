@@ -162,6 +162,8 @@ int launch_batch_steps(sfseg_ctx* ctx, int first_parity, int count) {
     for (int i = 0; i < count; ++i) {
         HIP_TRY(sfseg::launch_batch_step(ctx->cfg.storage, ctx->shape, ctx->cfg.r_s, ctx->cfg.r_t,
                                          b.params[(first_parity + i) & 1], b.grid, ctx->stream));
+        HIP_TRY(sfseg::launch_batch_finish(b.d_clips, (int)b.h_clips.size(), b.d_partials,
+                                           b.d_queue, ctx->stream));
     }
     return SFSEG_OK;
 }

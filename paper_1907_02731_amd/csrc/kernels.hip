@@ -228,6 +228,20 @@ __global__ __launch_bounds__(256) void step_finish(DevState* st2, int slot, cons
     }
 }
 
+// Block i: fold clip i's item partial sums into its state if it was iterating;
+// block 0 also resets the work queues for the next batched step.
+__global__ __launch_bounds__(256) void batch_finish(const BatchClip* clips, const double* partials,
+                                                    uint32_t* queue) {
+    __shared__ double red[2][4];
+    const BatchClip& cl = clips[blockIdx.x];
+    DevState* st = cl.st;
+    if (blockIdx.x == 0 && threadIdx.x < 9) queue[threadIdx.x] = 0u;
+    if (st->done) return;
+    double syy, syx;
+    detail::fold_partials<256>(partials + 2 * (int64_t)cl.first_item, cl.n_items, red, syy, syx);
+    if (threadIdx.x == 0) detail::advance_state(st, syy, syx);
+}
+
 // 2D grid of at most `blocks` blocks for the element-wise kernels.
 dim3 ew_dims(const Layout& L, int blocks) {
     const int gy = L.T < blocks ? L.T : blocks;
@@ -311,6 +325,13 @@ hipError_t step_max_blocks_per_cu(int dtype, int shape, int rs, int rt, int* blo
         default:                                      \
             return hipErrorInvalidValue;              \
     }
+
+hipError_t launch_batch_finish(const BatchClip* clips, int n_clips, const double* partials,
+                               uint32_t* queue, hipStream_t stream) {
+    if (n_clips < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(batch_finish, dim3(n_clips), dim3(256), 0, stream, clips, partials, queue);
+    return hipGetLastError();
+}
 
 hipError_t launch_step_finish(DevState* st2, int slot, const double* part, int nblocks,
                               hipStream_t stream) {

@@ -22,7 +22,8 @@ namespace sfseg {
 // blocks adds them in the same fixed order, so all take the same scale and
 // the same stop decision, and block 0 records the result.  No block waits on
 // another inside a launch, so no launch needs a device-wide memory fence.
-// Batched clips keep one slot each and fold in the launch's last block.
+// Batched clips keep one slot each; a one-block-per-clip launch after each
+// batched step folds them.
 struct DevState {
     double s;       // 1 / ||Y_k||
     double lambda;  // x_{k-1}^T M x_{k-1} of the last step
@@ -35,7 +36,7 @@ struct DevState {
     int32_t done;       // 1: later step launches return at once
     int32_t status;     // SFSEG_OK or the error that stopped the iteration
     int32_t converged;  // delta < tol reached
-    uint32_t ticket;    // arrival counter of a launch that folds in its last block
+    uint32_t ticket;    // unused (kept zero)
     int32_t pending;    // 1: the partial sums of the step that wrote this slot's buffer
                         // are not folded in yet (single clips)
 };
@@ -88,7 +89,7 @@ struct BatchParams {
     const BatchClip* clips;
     const int4* items;    // {clip, x0 | y0 << 16, t0, t1}
     double* partials;     // 2 doubles per item
-    uint32_t* queue;      // [0..7] next offset in each XCD's run, [8] blocks that left
+    uint32_t* queue;      // [0..7] next offset in each XCD's run, [8] unused
     int32_t qfirst[8];    // first item of each XCD's run
     int32_t qcount[8];    // items in each XCD's run
     int32_t parity;       // clips still iterating read buf[parity], write buf[1 - parity]
@@ -119,6 +120,10 @@ hipError_t step_max_blocks_per_cu(int dtype, int shape, int rs, int rt, int* blo
 hipError_t launch_batch_step(int dtype, int shape, int rs, int rt, const BatchParams& p, int grid,
                              hipStream_t stream);
 hipError_t batch_max_blocks_per_cu(int dtype, int shape, int rs, int rt, int* blocks);
+// After each batched step: one block per clip folds the partial sums of each
+// clip that was iterating into its state; block 0 resets the 9 queue counters.
+hipError_t launch_batch_finish(const BatchClip* clips, int n_clips, const double* partials,
+                               uint32_t* queue, hipStream_t stream);
 
 // Element-wise kernels between unpadded float32 volumes (the ABI) and padded
 // storage volumes (the library's internal layout).

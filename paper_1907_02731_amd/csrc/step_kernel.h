@@ -210,40 +210,6 @@ __device__ double fixed_order_sum(const double* partials, int nblocks, int first
     return r;
 }
 
-// Block-wide sums of a and b written to partials[2*slot], partials[2*slot+1];
-// returns true in every thread of the last block of the launch to arrive.
-template <int NT>
-__device__ bool block_partials_and_ticket(double a, double b, double* partials, int slot,
-                                          uint32_t* ticket, uint32_t nblocks) {
-    __shared__ double red[2][NT / 64];
-    __shared__ int is_last;
-    a = wave_sum(a);
-    b = wave_sum(b);
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    if (lane == 0) {
-        red[0][wid] = a;
-        red[1][wid] = b;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double sa = 0.0, sb = 0.0;
-#pragma unroll
-        for (int i = 0; i < NT / 64; ++i) {
-            sa += red[0][i];
-            sb += red[1][i];
-        }
-        agent_store(partials + 2 * slot, sa);
-        agent_store(partials + 2 * slot + 1, sb);
-        __threadfence();
-        const uint32_t t = atomicAdd(ticket, 1u);
-        is_last = (t == nblocks - 1);
-    }
-    __syncthreads();
-    const bool last = is_last != 0;
-    if (last) __threadfence();
-    return last;
-}
-
 // Advance the iteration state after a step.
 //   syy = sum(y_i^2), syx = sum(y_i * Y_k,i) over the stored values, where
 //   y = c * M Y_k and x_k = s * Y_k.  Then
@@ -277,7 +243,7 @@ __device__ inline void advance_values(DevState& st, double syy, double syx) {
     if (st.k >= st.max_iters) st.done = 1;
 }
 
-// The same on a state in memory; run by thread 0 of the last block.
+// The same on a state in memory (one thread of a finish launch).
 __device__ inline void advance_state(DevState* st, double syy, double syx) {
     advance_values(*st, syy, syx);
 }
@@ -434,15 +400,11 @@ struct Geom {
 };
 
 // LDS of one block: the raw x, w, F of the tile plus halo for one frame
-// (filled by direct-to-LDS loads) and the y-filtered fields.  The raw region
-// doubles as the scratch of the final fixed-order reduction.
+// (filled by direct-to-LDS loads) and the y-filtered fields.
 template <typename TS, int RS, int RT, typename SH>
 struct StepLds {
     using G = Geom<TS, RS, RT, SH>;
-    union {
-        TS raw[G::NARR][G::RAWE];
-        double fin[G::NT];
-    } __attribute__((aligned(16)));
+    TS raw[G::NARR][G::RAWE] __attribute__((aligned(16)));
     float mid3[G::NFLD][TY * G::MP] __attribute__((aligned(16)));
     TS own[G::OWN_LDS ? G::RT1 : 1][G::NARR][G::OWN_LDS ? TY * TX : 4] __attribute__((aligned(16)));
 };
@@ -756,9 +718,10 @@ __global__ __launch_bounds__(SH::NT, (Geom<TS, RS, RT, SH>::MINW)) void step_ker
 // queues, one per XCD: queue x holds a contiguous run of items (neighbouring
 // tiles of one clip, so their halos meet in that XCD's L2).  A block drains
 // the queue of its own XCD first, then takes leftovers from the others.  Each
-// item writes its partial sums to its own slot; the last item of a clip to
-// finish reduces that clip's slots in a fixed order and advances only that
-// clip's state, so a converged clip drops out of the next launch.
+// item writes its partial sums to its own slot and nothing else; the
+// one-block-per-clip finish launch that follows folds each iterating clip's
+// slots in a fixed order, advances only that clip's state (so a converged
+// clip drops out of the next launch) and resets the queues.
 template <typename TS, int RS, int RT, typename SH>
 __global__ __launch_bounds__(SH::NT, (Geom<TS, RS, RT, SH>::MINW)) void batch_step_kernel(BatchParams p) {
     using G = Geom<TS, RS, RT, SH>;
@@ -794,7 +757,7 @@ __global__ __launch_bounds__(SH::NT, (Geom<TS, RS, RT, SH>::MINW)) void batch_st
 
         const int4 item = p.items[it];  // clip, x0 | y0 << 16, t0, t1
         const BatchClip* cl = p.clips + item.x;
-        DevState* st = cl->st;
+        const DevState* st = cl->st;
         if (st->done) continue;  // converged or stopped: nothing to do for this clip
 
         const float c = st->c;
@@ -806,25 +769,7 @@ __global__ __launch_bounds__(SH::NT, (Geom<TS, RS, RT, SH>::MINW)) void batch_st
                                  (const TS*)cl->f, 0, (TS*)cl->buf[1 - p.parity], cl->T, cl->Wp,
                                  cl->PT, cl->PL, cl->frame, item.y & 0xffff, item.y >> 16, item.z,
                                  item.w, gs, gt, p.alpha, lds, syy, syx);
-        if (block_partials_and_ticket<NT>(syy, syx, p.partials, it, &st->ticket,
-                                          (uint32_t)cl->n_items)) {
-            const double* part = p.partials + 2 * cl->first_item;
-            const double tyy = fixed_order_sum<NT>(part, cl->n_items, 0, lds.fin);
-            const double tyx = fixed_order_sum<NT>(part, cl->n_items, 1, lds.fin);
-            if (threadIdx.x == 0) {
-                advance_state(st, tyy, tyx);
-                __hip_atomic_store(&st->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-        }
-    }
-    // The last block to leave resets the queues for the next launch.
-    if (threadIdx.x == 0) {
-        __threadfence();
-        if (atomicAdd(&p.queue[8], 1u) == gridDim.x - 1) {
-#pragma unroll
-            for (int i = 0; i < 9; ++i)
-                __hip_atomic_store(&p.queue[i], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
+        block_partials<NT>(syy, syx, p.partials, it);
     }
 }
 
