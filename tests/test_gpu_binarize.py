@@ -94,14 +94,21 @@ def _check_mask(m, x, ref, thr):
     assert m.any() and not m.all()
 
 
-def test_without_projection_is_the_plain_iteration(tiny):
+@pytest.mark.parametrize("iters", [6, 20, 37])
+def test_without_projection_is_the_plain_iteration(tiny, iters):
+    # Algorithm 1 folds every step's sums inside the next step launch;
+    # power iteration runs captured chunks of 16 steps and folds the last
+    # step of each chunk in a one-block launch.  The fold is the same fixed
+    # order wherever it runs, so the two agree bit for bit.
     S, _ = tiny
     with _solver(S) as sol:
-        sol.segment(iters=6, project_from=6, mask=False)
+        ra, _ = sol.segment(iters=iters, project_from=iters, mask=False)
         a = _f64(sol.eigvec())
-        sol.iterate(max_iters=6, tol=0.0)
+        rb = sol.iterate(max_iters=iters, tol=0.0)
         b = _f64(sol.eigvec())
     np.testing.assert_array_equal(a, b)
+    assert ra.iters == rb.iters == iters
+    assert ra.lam == rb.lam and ra.delta == rb.delta
 
 
 def test_threshold_is_exact_on_a_stored_iterate():
