@@ -732,23 +732,36 @@ __global__ __launch_bounds__(SH::NT, (Geom<TS, RS, RT, SH>::MINW)) void batch_st
     float gs[RS + 1];
 #pragma unroll
     for (int d = 0; d <= RS; ++d) gs[d] = p.gs[d];
-    const int home = blockIdx.x & 7;
-    int q = home;  // queue being drained
-    int tried = 0;
+    int q = blockIdx.x & 7;  // queue being drained: the block's own XCD's first
 
     for (;;) {
-        if (threadIdx.x == 0) {
+        // Wave 0 takes the next item: an atomic on queue q; once q has run
+        // dry, one look at all eight counters at once (lanes 0-7) moves it to
+        // the first queue after q that still has items, so the end of a
+        // launch costs one round trip per block instead of eight.  A failed
+        // atomic leaves its queue dry for good (counters only grow), so at
+        // most eight attempts fail before every queue reads empty.
+        if (threadIdx.x < 64) {
+            const int lane = threadIdx.x;
             int it = -1;
-            while (tried < 8) {
-                const uint32_t k = atomicAdd(&p.queue[q], 1u);
-                if ((int)k < p.qcount[q]) {
-                    it = p.qfirst[q] + (int)k;
-                    break;
+            for (int attempt = 0; attempt < 9; ++attempt) {
+                if (lane == 0) {
+                    const uint32_t k = atomicAdd(&p.queue[q], 1u);
+                    it = (int)k < p.qcount[q] ? p.qfirst[q] + (int)k : -1;
                 }
-                q = (q + 1) & 7;
-                ++tried;
+                it = __shfl(it, 0, 64);
+                if (it >= 0) break;
+                int left = 0;
+                if (lane < 8) {
+                    const int qq = (q + 1 + lane) & 7;
+                    left = __hip_atomic_load(&p.queue[qq], __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT) < (uint32_t)p.qcount[qq];
+                }
+                const uint64_t m = __ballot(left);
+                if (m == 0) break;  // every queue is empty
+                q = (q + 1 + __builtin_ctzll(m)) & 7;
             }
-            s_item = it;
+            if (lane == 0) s_item = it;
         }
         __syncthreads();
         const int it = s_item;
