@@ -147,3 +147,25 @@ def test_autotune_single_and_batch_with_cache(clips, tmp_path):
         pb = bs.autotune(steps=3, cache=cache)
         assert pb["threads"] in (256, 512)
     assert len(json.load(open(cache))) == 2
+
+
+def test_batch_at_real_resolutions_matches_the_oracle():
+    """Three clips at the batch workload's resolutions (240x427, 360x640,
+    480x854) with the full-size graph (r_s = 5, r_t = 2, sigma_s = 2,
+    sigma_t = 1): each clip's iterate after 3 batched steps against the
+    matrix-free FP64 oracle."""
+    from oracle.native import MatrixFree
+    full = OracleConfig(r_t=2, r_s=5, sigma_t=1.0, sigma_s=2.0, alpha=1.0, p=0.2)
+    shapes = [(20, 240, 427), (12, 360, 640), (8, 480, 854)]
+    Ss = [make_clip(*sh, seed=700 + i, dtype=np.float32) for i, sh in enumerate(shapes)]
+    K = 3
+    with BatchSolver([_t(S) for S in Ss], r_t=2, r_s=5, sigma_t=1.0, sigma_s=2.0, alpha=1.0,
+                     p=0.2) as bs:
+        res = bs.iterate(max_iters=K, tol=0.0)
+        xs = [x.cpu().numpy().astype(np.float64).ravel() for x in bs.eigvecs()]
+    for S, r, x in zip(Ss, res, xs):
+        mf = MatrixFree(S, None, full)
+        ref = power_iteration(mf.apply, S.astype(np.float64).ravel(), K, 0.0)
+        assert r.iters == K
+        assert np.linalg.norm(x - ref["x"]) <= 1e-5
+        assert abs(r.lam - ref["lam"]) <= 1e-6 * ref["lam"]
