@@ -63,6 +63,9 @@ def roofline(kernel: str, voxels: float, seconds: float, storage: str, r_s: int,
                    "measured": None if traffic is None else traffic / seconds / 1e9}}
     return out
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_full_traffic.json")
+# Work plans the autotuner chose on this GPU, keyed by clip shape, radii,
+# storage and feature channels; reused so that repeated runs time the same plan.
+PLAN_CACHE = os.path.join(ROOT, "paper_1907_02731_amd", "tuned_plans.json")
 KERNEL_SOURCES = ["paper_1907_02731_amd/csrc/step_kernel.h", "paper_1907_02731_amd/csrc/step_f32.hip",
                   "paper_1907_02731_amd/csrc/sfseg_internal.h"]
 
@@ -76,9 +79,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str, storage: str, nf: int = 1):
+def measured_traffic(workload: str, storage: str, nf: int = 1, plan=None):
     """HBM bytes per step-kernel launch from the committed counter summary,
-    if it was taken on the kernel sources as they are now (else None)."""
+    if it was taken on the kernel sources as they are now and with the same
+    work plan (else None)."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
@@ -88,7 +92,11 @@ def measured_traffic(workload: str, storage: str, nf: int = 1):
         return None
     key = f"{workload}/{storage}" + ("" if nf == 1 else f"/nf{nf}")
     entry = t.get("workloads", {}).get(key)
-    return None if entry is None else entry.get("hbm_bytes_per_launch")
+    if entry is None:
+        return None
+    if plan is not None and entry.get("plan") != [plan["shape"], plan["chunks"]]:
+        return None
+    return entry.get("hbm_bytes_per_launch")
 BYTES_PER_VOXEL = {"f32": 16, "bf16": 8, "f16": 8}
 
 WORKLOADS = {
@@ -109,7 +117,11 @@ def parse():
                          "(frames 20-100, 240x427 / 360x640 / 480x854) in one batched solve, "
                          "timed against solving them one by one")
     ap.add_argument("--clips", type=int, default=24, help="clips in the batch workload")
-    ap.add_argument("--autotune", action="store_true", help="autotune the work plan first")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="keep the library's default work plan instead of the autotuner's "
+                         "(which runs outside the timed region, or comes from the plan cache)")
+    ap.add_argument("--plan-cache", default=PLAN_CACHE,
+                    help="JSON file of tuned plans ('' to always time the plans afresh)")
     ap.add_argument("--storage", choices=["f32", "bf16", "f16"], default="f32")
     ap.add_argument("--tol", type=float, default=1e-5)
     ap.add_argument("--max-iters", type=int, default=5000)
@@ -201,7 +213,7 @@ def bench_batch(args):
               storage=args.storage)
     max_iters, tol = (args.iters, 0.0) if args.iters > 0 else (args.max_iters, args.tol)
     bs = BatchSolver(clips, **kw)
-    plan_info = bs.autotune(steps=4) if args.autotune else None
+    plan_info = bs.autotune(steps=16, cache=args.plan_cache or None) if args.autotune else None
     if args.shape >= 0 or args.chunks > 0:
         pl = bs.plan()
         bs.set_plan(args.shape if args.shape >= 0 else pl["shape"],
@@ -342,6 +354,7 @@ def bench_segment(args):
     kw = dict(r_t=r_t, r_s=r_s, sigma_t=s_t, sigma_s=s_s, alpha=args.alpha, p=args.p,
               storage=args.storage)
     sol = Solver(St, **kw)
+    plan_info = sol.autotune(steps=32, cache=args.plan_cache or None) if args.autotune else None
 
     def one_step():
         sol.set_features(St)
@@ -395,9 +408,11 @@ def bench_segment(args):
                    "T": T, "H": H, "W": W, "iters": iters, "project_from": k0,
                    "slope": slope, "threshold": thr},
         "lambda": last.lam, "delta": last.delta,
+        "plan": sol.plan(), "autotune": plan_info,
         "mask_fraction": float(mask.float().mean().item()),
         "roofline": roofline("step_kernel (fused stencil + reductions)", N, step_s,
-                             args.storage, r_s, r_t, measured_traffic("full", args.storage)),
+                             args.storage, r_s, r_t,
+                             measured_traffic("full", args.storage, 1, sol.plan())),
         "binarize": {
             "project_us": proj_s * 1e6, "project_bytes": proj_bytes,
             "project_GBps": proj_bytes / proj_s / 1e9,
@@ -473,7 +488,7 @@ def main():
     kw = dict(r_t=r_t, r_s=r_s, sigma_t=s_t, sigma_s=s_s, alpha=args.alpha, p=args.p,
               storage=args.storage)
     sol = Solver(St, Ft, **kw)
-    plan_info = sol.autotune(steps=8) if args.autotune else None
+    plan_info = sol.autotune(steps=32, cache=args.plan_cache or None) if args.autotune else None
     if args.shape >= 0 or args.chunks > 0:
         pl = sol.plan()
         sol.set_plan(args.shape if args.shape >= 0 else pl["shape"],
@@ -532,7 +547,7 @@ def main():
         "time_to_converge_ms": elapsed * 1e3 / args.steps,
         "roofline": roofline("step_kernel (fused stencil + reductions)", N, avg_kernel_s,
                              args.storage, r_s, r_t,
-                             measured_traffic(args.workload, args.storage, nf),
+                             measured_traffic(args.workload, args.storage, nf, sol.plan()),
                              nf=nf),
     }
     if args.precision_report:

@@ -357,7 +357,11 @@ using ShapeDeep2 = Shape<2, 2>;
 //      own x, w, F, rounds to the storage type and reduces.
 // The raw region of the next frame is loaded straight into LDS while the X
 // phase runs: the Y phase is its only reader and has finished.
-template <typename TS, int RS, int RT, typename SH>
+// OWN_MAX: the LDS bytes a block may reach with the own-value ring (see
+// OWN_LDS); beyond it the ring is left out.
+constexpr int kLdsThreeBlocks = 53 * 1024;  // three blocks share a CU's 160 KB
+constexpr int kLdsTwoBlocks = 80 * 1024;    // two blocks do
+template <typename TS, int RS, int RT, typename SH, int OWN_MAX = kLdsTwoBlocks>
 struct Geom {
     static constexpr int NT = SH::NT, PX = SH::PX, NSEG = SH::NSEG, NWAVES = SH::NWAVES;
     static constexpr int NF = SH::NF;                // pairwise feature channels
@@ -381,18 +385,23 @@ struct Geom {
     static constexpr int XWA = round4(PX + 2 * RS);  // x-pass window, whole 8/16-byte reads
     static constexpr int MP = TX - PX + XWA + (PX == 2 ? 2 : 0);  // y-filtered row pitch
     static constexpr int NR = 2 * RT + 1;            // frames in the register ring
-    // The tile's own x, w, F of the last r_t + 1 frames are kept in LDS (taken
-    // from the region while it is there) when that still lets two blocks share
-    // a CU; otherwise the output frame's values are read from memory.
+    // The tile's own x, w, F of the last r_t + 1 frames are kept in LDS
+    // (taken from the region while it is there) when the block stays within
+    // OWN_MAX bytes; otherwise the output frame's values are read from memory
+    // again r_t frames after the region brought them in (L2 hits only while
+    // the resident blocks' windows fit the XCD's L2).
     static constexpr int RT1 = RT + 1;                // frames in the own-value ring
     static constexpr int LDS_BASE = NARR * RAWE * ES + NFLD * TY * MP * 4;
-    static constexpr bool OWN_LDS = LDS_BASE + RT1 * NARR * TY * TX * ES <= 80 * 1024;
+    static constexpr int LDS_OWN = RT1 * NARR * TY * TX * ES;
+    static constexpr bool OWN_LDS = LDS_BASE + LDS_OWN <= OWN_MAX;
+    static constexpr int LDS_TOT = LDS_BASE + (OWN_LDS ? LDS_OWN : 0);
     // Waves per SIMD the register budget is set for (the second launch-bounds
-    // argument): with the own ring in LDS two blocks share a CU, so two waves
-    // per SIMD (for 256-thread blocks); otherwise three when the register ring
-    // is small enough.
+    // argument): three when three blocks fit the LDS and the register ring is
+    // small enough; otherwise two blocks share a CU (two waves per SIMD for
+    // 256-thread blocks).
     static constexpr int RING = NR * NFLD * PX;
-    static constexpr int MINW = OWN_LDS ? 2 * NT / 256 : (RING <= 84 ? 3 : 2);
+    static constexpr int MINW =
+        LDS_TOT <= kLdsThreeBlocks && RING <= 84 ? 3 : (OWN_LDS ? 2 * NT / 256 : 2);
     static_assert(NS >= 1 && NS * EXT <= 64 && NS + 1 <= NWAVES, "y-pass lane mapping");
     static_assert(NS * PY >= TY && PY <= TY, "segments cover the tile rows");
     static_assert(MP % 4 == 0, "aligned rows");
@@ -401,9 +410,9 @@ struct Geom {
 
 // LDS of one block: the raw x, w, F of the tile plus halo for one frame
 // (filled by direct-to-LDS loads) and the y-filtered fields.
-template <typename TS, int RS, int RT, typename SH>
+template <typename TS, int RS, int RT, typename SH, int OWN_MAX = kLdsTwoBlocks>
 struct StepLds {
-    using G = Geom<TS, RS, RT, SH>;
+    using G = Geom<TS, RS, RT, SH, OWN_MAX>;
     TS raw[G::NARR][G::RAWE] __attribute__((aligned(16)));
     float mid3[G::NFLD][TY * G::MP] __attribute__((aligned(16)));
     TS own[G::OWN_LDS ? G::RT1 : 1][G::NARR][G::OWN_LDS ? TY * TX : 4] __attribute__((aligned(16)));
@@ -419,14 +428,15 @@ struct StepLds {
 // the own ring; Y phase; barrier; X phase, with the region loads of frame
 // t + 1 (16 bytes per lane straight into LDS) issued one array per field; t
 // filter, combine with the own x, w, F of frame t - r_t, and reduce.
-template <typename TS, int RS, int RT, typename SH>
+template <typename TS, int RS, int RT, typename SH, int OWN_MAX>
 __device__ __forceinline__ void run_item(const TS* __restrict__ X, const TS* __restrict__ Wt,
                                          const TS* __restrict__ Fv, int64_t fstride,
                                          TS* __restrict__ Y, int T, int Wp, int PT, int PL,
                                          int64_t frame, int tx0, int ty0, int ta, int tb,
                                          const float* gs, const float* gt, float alpha,
-                                         StepLds<TS, RS, RT, SH>& lds, double& syy, double& syx) {
-    using G = Geom<TS, RS, RT, SH>;
+                                         StepLds<TS, RS, RT, SH, OWN_MAX>& lds, double& syy,
+                                         double& syx) {
+    using G = Geom<TS, RS, RT, SH, OWN_MAX>;
     constexpr int NT = G::NT, PX = G::PX, NSEG = G::NSEG, IW = G::IW, EXT = G::EXT,
                   NS = G::NS, PY = G::PY, YW = G::YW, XWA = G::XWA, MP = G::MP, NR = G::NR,
                   RSA = G::RSA, IWA = G::IWA, CPR = G::CPR, NCH = G::NCH, NDMA = G::NDMA,
@@ -677,11 +687,21 @@ __device__ __forceinline__ void run_item(const TS* __restrict__ X, const TS* __r
     __syncthreads();  // the last region loads have landed before LDS is reused
 }
 
+// The single-clip kernel keeps the own-value ring only where three blocks
+// still share a CU (16-bit storage): plans that cut each tile's frames into
+// several runs (more, shorter blocks) then fill the chip and balance it,
+// while with only two blocks per CU they lose.  For float32 the ring would
+// leave room for two blocks, so the own values are read again instead.  The
+// batched kernel, whose many clips already fill the chip, keeps the ring
+// wherever two blocks fit.
+constexpr int kStepOwnMax = kLdsThreeBlocks;
+
 template <typename TS, int RS, int RT, typename SH>
-__global__ __launch_bounds__(SH::NT, (Geom<TS, RS, RT, SH>::MINW)) void step_kernel(StepParams p) {
-    using G = Geom<TS, RS, RT, SH>;
+__global__ __launch_bounds__(SH::NT, (Geom<TS, RS, RT, SH, kStepOwnMax>::MINW))
+void step_kernel(StepParams p) {
+    using G = Geom<TS, RS, RT, SH, kStepOwnMax>;
     constexpr int NT = G::NT, NR = G::NR;
-    __shared__ StepLds<TS, RS, RT, SH> lds;
+    __shared__ StepLds<TS, RS, RT, SH, kStepOwnMax> lds;
     __shared__ double fold_red[2][4];
 
     // Fold the previous step's partial sums (every block, same bits), record
@@ -705,9 +725,10 @@ __global__ __launch_bounds__(SH::NT, (Geom<TS, RS, RT, SH>::MINW)) void step_ker
     const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
     const int4 item = p.items[lb];  // tile origin (picture coords) and frame range
     double syy = 0.0, syx = 0.0;
-    run_item<TS, RS, RT, SH>((const TS*)p.x, (const TS*)p.w, (const TS*)p.f, p.fstride,
-                             (TS*)p.y, p.T, p.Wp, p.PT, p.PL, p.frame, item.x, item.y, item.z,
-                             item.w, gs, gt, p.alpha, lds, syy, syx);
+    run_item<TS, RS, RT, SH, kStepOwnMax>((const TS*)p.x, (const TS*)p.w, (const TS*)p.f,
+                                           p.fstride, (TS*)p.y, p.T, p.Wp, p.PT, p.PL, p.frame,
+                                           item.x, item.y, item.z, item.w, gs, gt, p.alpha, lds,
+                                           syy, syx);
     block_partials<NT>(syy, syx, p.part_out, lb);
 }
 
@@ -778,7 +799,7 @@ __global__ __launch_bounds__(SH::NT, (Geom<TS, RS, RT, SH>::MINW)) void batch_st
 #pragma unroll
         for (int m = 0; m < NR; ++m) gt[m] = p.gt[m < RT ? RT - m : m - RT] * c;
         double syy = 0.0, syx = 0.0;
-        run_item<TS, RS, RT, SH>((const TS*)cl->buf[p.parity], (const TS*)cl->w,
+        run_item<TS, RS, RT, SH, kLdsTwoBlocks>((const TS*)cl->buf[p.parity], (const TS*)cl->w,
                                  (const TS*)cl->f, 0, (TS*)cl->buf[1 - p.parity], cl->T, cl->Wp,
                                  cl->PT, cl->PL, cl->frame, item.y & 0xffff, item.y >> 16, item.z,
                                  item.w, gs, gt, p.alpha, lds, syy, syx);

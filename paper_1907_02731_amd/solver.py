@@ -220,7 +220,8 @@ def _autotune(solver, steps: int, cache: Optional[str], shapes) -> dict:
     remember it in `cache`, a JSON file of {key: [shape, chunks]}."""
     c = solver.cfg
     key = json.dumps({"shapes": [list(s) for s in shapes], "r_t": c.r_t, "r_s": c.r_s,
-                      "storage": c.storage, "arch": _arch(solver.device)}, sort_keys=True)
+                      "storage": c.storage, "features": int(getattr(solver, "n_features", 1)),
+                      "arch": _arch(solver.device)}, sort_keys=True)
     table = {}
     if cache and os.path.exists(cache):
         with open(cache) as fh:
