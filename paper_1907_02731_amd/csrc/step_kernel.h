@@ -464,8 +464,9 @@ __device__ __forceinline__ void run_item(const TS* __restrict__ X, const TS* __r
         const bool tin = t >= 0 && t < T;
         return make_rsrc(base + (tin ? (int64_t)t * frame : 0), tin ? frame_bytes : 0u);
     };
-    // Array a (x, w or F) of the region of frame t into raw; frames outside
-    // the clip are zeros.
+    // Array a (x, w or F) of the region of frame t into raw.  Frames outside
+    // the clip are zeros: nothing reads raw for them (their steps skip the y
+    // and x passes), so nothing is loaded.
     auto load_region_array = [&](int t, int a) {
         if (t >= 0 && t < T) {
             const __amdgpu_buffer_rsrc_t rr =
@@ -475,8 +476,6 @@ __device__ __forceinline__ void run_item(const TS* __restrict__ X, const TS* __r
                 if (r * NT + tid < NCH)
                     load_lds16(rr, &lds.raw[a][(r * NT + wave * 64) * (16 / ES)], doff[r]);
             }
-        } else {
-            for (int e = tid; e < RAWE; e += NT) lds.raw[a][e] = (TS)0.f;
         }
     };
 
@@ -550,8 +549,9 @@ __device__ __forceinline__ void run_item(const TS* __restrict__ X, const TS* __r
     float yv[PX];          // outputs waiting to be stored
     int pending_t = -1;    // their frame (-1: none)
 
-    // Input frames ta-RT .. tb+RT-1, rounded up to whole ring turns; the
-    // extra steps read frames past the run and store nothing.
+    // Input frames ta-RT .. tb+RT-1.  The loop runs in whole ring turns (the
+    // ring slot is then a compile-time index) and leaves the last turn as
+    // soon as the run's input frames are done.
     const int n_in = (tb - ta) + 2 * RT;
     const int n_steps = (n_in + NR - 1) / NR * NR;
 #pragma unroll
@@ -560,6 +560,7 @@ __device__ __forceinline__ void run_item(const TS* __restrict__ X, const TS* __r
     for (int s0 = 0; s0 < n_steps; s0 += NR) {
 #pragma unroll
         for (int j = 0; j < NR; ++j) {
+            if (s0 + j >= n_in) break;  // uniform over the block
             const int t_in = ta - RT + s0 + j;
             asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
             __syncthreads();  // raw holds frame t_in; mid3 is free
@@ -571,81 +572,103 @@ __device__ __forceinline__ void run_item(const TS* __restrict__ X, const TS* __r
             const int t_out = t_in - RT;
             const bool emit = t_out >= ta && t_out < tb;
             if (t_in >= ta && t_in < tb) save_own(t_in);
-            // ---- Y phase: fields, filtered along y, into mid3 ----
-            if (yact) {
-                const TS* rx = &lds.raw[0][ybase];
-                const TS* rw = &lds.raw[1][ybase];
-                float acc[NFLD][PY];
+            // A frame outside the clip is all zeros, and so are its filtered
+            // fields: its ring slot is cleared instead of running the y and x
+            // passes (uniform over the block, like every branch around a
+            // barrier here).
+            const bool zero = t_in < 0 || t_in >= T;
+            const bool more = s0 + j + 1 < n_in;  // the run reads frame t_in + 1
+            if (!zero) {
+                // ---- Y phase: fields, filtered along y, into mid3 ----
+                if (yact) {
+                    const TS* rx = &lds.raw[0][ybase];
+                    const TS* rw = &lds.raw[1][ybase];
+                    float acc[NFLD][PY];
 #pragma unroll
-                for (int f = 0; f < NFLD; ++f)
+                    for (int f = 0; f < NFLD; ++f)
 #pragma unroll
-                    for (int i = 0; i < PY; ++i) acc[f][i] = 0.f;
+                        for (int i = 0; i < PY; ++i) acc[f][i] = 0.f;
 #pragma unroll
-                for (int k = 0; k < YW; ++k) {
-                    // fields: u, then F_c u and F_c^2 u for each channel c
-                    float fld[NFLD];
-                    fld[0] = (float)rw[k * IWA] * (float)rx[k * IWA];
+                    for (int k = 0; k < YW; ++k) {
+                        // fields: u, then F_c u and F_c^2 u for each channel c
+                        float fld[NFLD];
+                        fld[0] = (float)rw[k * IWA] * (float)rx[k * IWA];
 #pragma unroll
-                    for (int c = 0; c < NF; ++c) {
-                        const float fv = (float)lds.raw[2 + c][ybase + k * IWA];
-                        fld[1 + 2 * c] = fv * fld[0];
-                        fld[2 + 2 * c] = fv * fld[1 + 2 * c];
+                        for (int c = 0; c < NF; ++c) {
+                            const float fv = (float)lds.raw[2 + c][ybase + k * IWA];
+                            fld[1 + 2 * c] = fv * fld[0];
+                            fld[2 + 2 * c] = fv * fld[1 + 2 * c];
+                        }
+#pragma unroll
+                        for (int i = 0; i < PY; ++i) {
+                            const int d = k - i - RS;  // tap offset, constant once unrolled
+                            if (d >= -RS && d <= RS) {
+                                const float g = gs[d < 0 ? -d : d];
+#pragma unroll
+                                for (int f = 0; f < NFLD; ++f) acc[f][i] = fmaf(g, fld[f], acc[f][i]);
+                            }
+                        }
                     }
 #pragma unroll
                     for (int i = 0; i < PY; ++i) {
-                        const int d = k - i - RS;  // tap offset, constant once unrolled
-                        if (d >= -RS && d <= RS) {
-                            const float g = gs[d < 0 ? -d : d];
+                        if (i >= yskip) {
+                            const int o = (ys + i) * MP + ycol;
 #pragma unroll
-                            for (int f = 0; f < NFLD; ++f) acc[f][i] = fmaf(g, fld[f], acc[f][i]);
+                            for (int f = 0; f < NFLD; ++f) lds.mid3[f][o] = acc[f][i];
                         }
                     }
                 }
+                __syncthreads();  // mid3 is complete; raw is free
+                if constexpr (!G::OWN_LDS) {
+                    if (emit) load_own(t_out);
+                }
+                // ---- X phase: filter along x into ring slot j; the region loads
+                // of frame t_in + 1 (if the run reads it) are issued one array per
+                // field ----
 #pragma unroll
-                for (int i = 0; i < PY; ++i) {
-                    if (i >= yskip) {
-                        const int o = (ys + i) * MP + ycol;
+                for (int f = 0; f < NFLD; ++f) {
+                    if (f < NARR && more) load_region_array(t_in + 1, f);
+                    float win[XWA];
+                    const float* src = &lds.mid3[f][orow * MP + ocol];
+                    if constexpr (PX % 4 == 0) {
 #pragma unroll
-                        for (int f = 0; f < NFLD; ++f) lds.mid3[f][o] = acc[f][i];
+                        for (int q = 0; q < XWA / 4; ++q) {
+                            const float4 v4 = reinterpret_cast<const float4*>(src)[q];
+                            win[4 * q + 0] = v4.x;
+                            win[4 * q + 1] = v4.y;
+                            win[4 * q + 2] = v4.z;
+                            win[4 * q + 3] = v4.w;
+                        }
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < XWA / 2; ++q) {
+                            const float2 v2 = reinterpret_cast<const float2*>(src)[q];
+                            win[2 * q + 0] = v2.x;
+                            win[2 * q + 1] = v2.y;
+                        }
+                    }
+#pragma unroll
+                    for (int i = 0; i < PX; ++i) {
+                        float a = gs[0] * win[i + RS];
+#pragma unroll
+                        for (int d = 1; d <= RS; ++d)
+                            a = fmaf(gs[d], win[i + RS - d] + win[i + RS + d], a);
+                        ring[j][f][i] = a;
                     }
                 }
-            }
-            __syncthreads();  // mid3 is complete; raw is free
-            if constexpr (!G::OWN_LDS) {
-                if (emit) load_own(t_out);
-            }
-            // ---- X phase: filter along x into ring slot j; the region loads
-            // of frame t_in + 1 are issued one array per field ----
-#pragma unroll
-            for (int f = 0; f < NFLD; ++f) {
-                if (f < NARR) load_region_array(t_in + 1, f);
-                float win[XWA];
-                const float* src = &lds.mid3[f][orow * MP + ocol];
-                if constexpr (PX % 4 == 0) {
-#pragma unroll
-                    for (int q = 0; q < XWA / 4; ++q) {
-                        const float4 v4 = reinterpret_cast<const float4*>(src)[q];
-                        win[4 * q + 0] = v4.x;
-                        win[4 * q + 1] = v4.y;
-                        win[4 * q + 2] = v4.z;
-                        win[4 * q + 3] = v4.w;
-                    }
-                } else {
-#pragma unroll
-                    for (int q = 0; q < XWA / 2; ++q) {
-                        const float2 v2 = reinterpret_cast<const float2*>(src)[q];
-                        win[2 * q + 0] = v2.x;
-                        win[2 * q + 1] = v2.y;
-                    }
+            } else {
+                if constexpr (!G::OWN_LDS) {
+                    if (emit) load_own(t_out);
                 }
+                // raw is free (nothing reads it for this frame): load the next
+                // region now
 #pragma unroll
-                for (int i = 0; i < PX; ++i) {
-                    float a = gs[0] * win[i + RS];
+                for (int f = 0; f < NARR; ++f)
+                    if (more) load_region_array(t_in + 1, f);
 #pragma unroll
-                    for (int d = 1; d <= RS; ++d)
-                        a = fmaf(gs[d], win[i + RS - d] + win[i + RS + d], a);
-                    ring[j][f][i] = a;
-                }
+                for (int f = 0; f < NFLD; ++f)
+#pragma unroll
+                    for (int i = 0; i < PX; ++i) ring[j][f][i] = 0.f;
             }
             // ---- filter along t, combine (Eq. (7)), reduce frame t_out ----
             if (emit) {
