@@ -156,7 +156,6 @@ __global__ __launch_bounds__(256) void init_finish(DevState* st, const double* p
             st->s = 1.0 / nrm;
             st->c = (float)(st->s * st->gain);
         }
-        st->ticket = 0u;
     }
 }
 

@@ -36,7 +36,6 @@ struct DevState {
     int32_t done;       // 1: later step launches return at once
     int32_t status;     // SFSEG_OK or the error that stopped the iteration
     int32_t converged;  // delta < tol reached
-    uint32_t ticket;    // unused (kept zero)
     int32_t pending;    // 1: the partial sums of the step that wrote this slot's buffer
                         // are not folded in yet (single clips)
 };
