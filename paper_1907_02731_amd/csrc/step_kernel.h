@@ -427,7 +427,8 @@ struct StepLds {
 // waits for a store just issued); keep the tile's own x, w, F of frame t in
 // the own ring; Y phase; barrier; X phase, with the region loads of frame
 // t + 1 (16 bytes per lane straight into LDS) issued one array per field; t
-// filter, combine with the own x, w, F of frame t - r_t, and reduce.
+// filter, combine with the own x, w, F of frame t - r_t, and reduce.  A frame
+// outside the clip skips the Y and X phases and clears its ring slot.
 template <typename TS, int RS, int RT, typename SH, int OWN_MAX>
 __device__ __forceinline__ void run_item(const TS* __restrict__ X, const TS* __restrict__ Wt,
                                          const TS* __restrict__ Fv, int64_t fstride,
