@@ -385,11 +385,10 @@ struct Geom {
     static constexpr int XWA = round4(PX + 2 * RS);  // x-pass window, whole 8/16-byte reads
     static constexpr int MP = TX - PX + XWA + (PX == 2 ? 2 : 0);  // y-filtered row pitch
     static constexpr int NR = 2 * RT + 1;            // frames in the register ring
-    // The tile's own x, w, F of the last r_t + 1 frames are kept in LDS
-    // (taken from the region while it is there) when the block stays within
-    // OWN_MAX bytes; otherwise the output frame's values are read from memory
-    // again r_t frames after the region brought them in (L2 hits only while
-    // the resident blocks' windows fit the XCD's L2).
+    // The tile's own x, w, F of the last r_t + 1 frames (taken from the
+    // region while it is in LDS) are kept in an LDS ring when the block stays
+    // within OWN_MAX bytes, otherwise in registers (NARR * PX more per frame
+    // of the ring).
     static constexpr int RT1 = RT + 1;                // frames in the own-value ring
     static constexpr int LDS_BASE = NARR * RAWE * ES + NFLD * TY * MP * 4;
     static constexpr int LDS_OWN = RT1 * NARR * TY * TX * ES;
@@ -497,9 +496,9 @@ __device__ __forceinline__ void run_item(const TS* __restrict__ X, const TS* __r
     const int ybase = ys * IWA + ycol + (RSA - RS);
     const int ooff = ((ty0 + PT + orow) * Wp + (tx0 + PL + ocol)) * ES;
 
-    // Own x, w, F of this thread's PX pixels: copied from the region into the
-    // own ring while the frame is in LDS (or, without the ring, read from
-    // memory when the frame is emitted).
+    // Own x, w, F of this thread's PX pixels: copied from the region while
+    // the frame is in LDS, into the LDS own ring or, without it, into a
+    // register shift ring of r_t + 1 frames (oR[0] is the output frame's).
     const int rown = (orow + RS) * IWA + RSA + ocol;  // own pixels inside the region
     const int town = orow * TX + ocol;                // own pixels inside the tile
     auto save_own = [&](int t) {
@@ -521,6 +520,7 @@ __device__ __forceinline__ void run_item(const TS* __restrict__ X, const TS* __r
         }
     };
     float qX[PX], qW[PX], qF[NF][PX];  // own x, w, F_c of the output frame
+    float oR[G::OWN_LDS ? 1 : G::RT1][NARR][PX];  // register own ring (no LDS ring)
     auto read_own = [&](int t) {
         const int slot = t % G::RT1;
 #pragma unroll
@@ -530,14 +530,6 @@ __device__ __forceinline__ void run_item(const TS* __restrict__ X, const TS* __r
 #pragma unroll
             for (int c = 0; c < NF; ++c) qF[c][i] = (float)lds.own[slot][2 + c][town + i];
         }
-    };
-    auto load_own = [&](int t) {
-        const __amdgpu_buffer_rsrc_t rx = rsrc(X, t), rw = rsrc(Wt, t);
-        Stor<TS>::template bloadn<PX>(rx, ooff, qX);
-        Stor<TS>::template bloadn<PX>(rw, ooff, qW);
-#pragma unroll
-        for (int c = 0; c < NF; ++c)
-            Stor<TS>::template bloadn<PX>(rsrc(Fv + (int64_t)c * fstride, t), ooff, qF[c]);
     };
 
     float ring[NR][NFLD][PX];  // x/y-filtered fields of the last NR frames
@@ -573,6 +565,20 @@ __device__ __forceinline__ void run_item(const TS* __restrict__ X, const TS* __r
             const int t_out = t_in - RT;
             const bool emit = t_out >= ta && t_out < tb;
             if (t_in >= ta && t_in < tb) save_own(t_in);
+            if constexpr (!G::OWN_LDS) {
+#pragma unroll
+                for (int q = 0; q < RT; ++q)
+#pragma unroll
+                    for (int ar = 0; ar < NARR; ++ar)
+#pragma unroll
+                        for (int i = 0; i < PX; ++i) oR[q][ar][i] = oR[q + 1][ar][i];
+                if (t_in >= ta && t_in < tb) {
+#pragma unroll
+                    for (int ar = 0; ar < NARR; ++ar)
+#pragma unroll
+                        for (int i = 0; i < PX; ++i) oR[RT][ar][i] = (float)lds.raw[ar][rown + i];
+                }
+            }
             // A frame outside the clip is all zeros, and so are its filtered
             // fields: its ring slot is cleared instead of running the y and x
             // passes (uniform over the block, like every branch around a
@@ -620,9 +626,6 @@ __device__ __forceinline__ void run_item(const TS* __restrict__ X, const TS* __r
                     }
                 }
                 __syncthreads();  // mid3 is complete; raw is free
-                if constexpr (!G::OWN_LDS) {
-                    if (emit) load_own(t_out);
-                }
                 // ---- X phase: filter along x into ring slot j; the region loads
                 // of frame t_in + 1 (if the run reads it) are issued one array per
                 // field ----
@@ -658,9 +661,6 @@ __device__ __forceinline__ void run_item(const TS* __restrict__ X, const TS* __r
                     }
                 }
             } else {
-                if constexpr (!G::OWN_LDS) {
-                    if (emit) load_own(t_out);
-                }
                 // raw is free (nothing reads it for this frame): load the next
                 // region now
 #pragma unroll
@@ -673,7 +673,17 @@ __device__ __forceinline__ void run_item(const TS* __restrict__ X, const TS* __r
             }
             // ---- filter along t, combine (Eq. (7)), reduce frame t_out ----
             if (emit) {
-                if constexpr (G::OWN_LDS) read_own(t_out);
+                if constexpr (G::OWN_LDS) {
+                    read_own(t_out);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < PX; ++i) {
+                        qX[i] = oR[0][0][i];
+                        qW[i] = oR[0][1][i];
+#pragma unroll
+                        for (int c = 0; c < NF; ++c) qF[c][i] = oR[0][2 + c][i];
+                    }
+                }
 #pragma unroll
                 for (int i = 0; i < PX; ++i) {
                     float tf[NFLD];  // A = G * u, then C_c = G * (F_c u), B_c = G * (F_c^2 u)
@@ -711,12 +721,12 @@ __device__ __forceinline__ void run_item(const TS* __restrict__ X, const TS* __r
     __syncthreads();  // the last region loads have landed before LDS is reused
 }
 
-// The single-clip kernel keeps the own-value ring only where three blocks
-// still share a CU (16-bit storage): plans that cut each tile's frames into
-// several runs (more, shorter blocks) then fill the chip and balance it,
-// while with only two blocks per CU they lose.  For float32 the ring would
-// leave room for two blocks, so the own values are read again instead.  The
-// batched kernel, whose many clips already fill the chip, keeps the ring
+// The single-clip kernel keeps the own-value ring in LDS only where three
+// blocks still share a CU (16-bit storage): plans that cut each tile's frames
+// into several runs (more, shorter blocks) then fill the chip and balance it,
+// while with only two blocks per CU they lose.  For float32 the LDS ring
+// would leave room for two blocks, so the own values ride in registers.  The
+// batched kernel, whose many clips already fill the chip, keeps the LDS ring
 // wherever two blocks fit.
 constexpr int kStepOwnMax = kLdsThreeBlocks;
 
