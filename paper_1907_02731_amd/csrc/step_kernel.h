@@ -357,11 +357,10 @@ using ShapeDeep2 = Shape<2, 2>;
 //      own x, w, F, rounds to the storage type and reduces.
 // The raw region of the next frame is loaded straight into LDS while the X
 // phase runs: the Y phase is its only reader and has finished.
-// OWN_MAX: the LDS bytes a block may reach with the own-value ring (see
-// OWN_LDS); beyond it the ring is left out.
+// OWN_MAX: the LDS bytes a block may reach with the own-value ring in LDS
+// (see OWN_LDS); beyond it the ring is kept in registers.
 constexpr int kLdsThreeBlocks = 53 * 1024;  // three blocks share a CU's 160 KB
-constexpr int kLdsTwoBlocks = 80 * 1024;    // two blocks do
-template <typename TS, int RS, int RT, typename SH, int OWN_MAX = kLdsTwoBlocks>
+template <typename TS, int RS, int RT, typename SH, int OWN_MAX>
 struct Geom {
     static constexpr int NT = SH::NT, PX = SH::PX, NSEG = SH::NSEG, NWAVES = SH::NWAVES;
     static constexpr int NF = SH::NF;                // pairwise feature channels
@@ -409,7 +408,7 @@ struct Geom {
 
 // LDS of one block: the raw x, w, F of the tile plus halo for one frame
 // (filled by direct-to-LDS loads) and the y-filtered fields.
-template <typename TS, int RS, int RT, typename SH, int OWN_MAX = kLdsTwoBlocks>
+template <typename TS, int RS, int RT, typename SH, int OWN_MAX>
 struct StepLds {
     using G = Geom<TS, RS, RT, SH, OWN_MAX>;
     TS raw[G::NARR][G::RAWE] __attribute__((aligned(16)));
@@ -721,13 +720,12 @@ __device__ __forceinline__ void run_item(const TS* __restrict__ X, const TS* __r
     __syncthreads();  // the last region loads have landed before LDS is reused
 }
 
-// The single-clip kernel keeps the own-value ring in LDS only where three
-// blocks still share a CU (16-bit storage): plans that cut each tile's frames
-// into several runs (more, shorter blocks) then fill the chip and balance it,
-// while with only two blocks per CU they lose.  For float32 the LDS ring
-// would leave room for two blocks, so the own values ride in registers.  The
-// batched kernel, whose many clips already fill the chip, keeps the LDS ring
-// wherever two blocks fit.
+// Both step kernels keep the own-value ring in LDS only where three blocks
+// still share a CU (16-bit storage); for float32 the LDS ring would leave
+// room for two blocks, so the own values ride in registers.  Three blocks
+// per CU let single-clip plans that cut each tile's frames into several runs
+// (more, shorter blocks) fill the chip and balance it, and give the batched
+// kernel's persistent grid 768 blocks instead of 512.
 constexpr int kStepOwnMax = kLdsThreeBlocks;
 
 template <typename TS, int RS, int RT, typename SH>
@@ -778,10 +776,10 @@ void step_kernel(StepParams p) {
 // slots in a fixed order, advances only that clip's state (so a converged
 // clip drops out of the next launch) and resets the queues.
 template <typename TS, int RS, int RT, typename SH>
-__global__ __launch_bounds__(SH::NT, (Geom<TS, RS, RT, SH>::MINW)) void batch_step_kernel(BatchParams p) {
-    using G = Geom<TS, RS, RT, SH>;
+__global__ __launch_bounds__(SH::NT, (Geom<TS, RS, RT, SH, kStepOwnMax>::MINW)) void batch_step_kernel(BatchParams p) {
+    using G = Geom<TS, RS, RT, SH, kStepOwnMax>;
     constexpr int NT = G::NT, NR = G::NR;
-    __shared__ StepLds<TS, RS, RT, SH> lds;
+    __shared__ StepLds<TS, RS, RT, SH, kStepOwnMax> lds;
     __shared__ int s_item;
 
     float gs[RS + 1];
@@ -833,7 +831,7 @@ __global__ __launch_bounds__(SH::NT, (Geom<TS, RS, RT, SH>::MINW)) void batch_st
 #pragma unroll
         for (int m = 0; m < NR; ++m) gt[m] = p.gt[m < RT ? RT - m : m - RT] * c;
         double syy = 0.0, syx = 0.0;
-        run_item<TS, RS, RT, SH, kLdsTwoBlocks>((const TS*)cl->buf[p.parity], (const TS*)cl->w,
+        run_item<TS, RS, RT, SH, kStepOwnMax>((const TS*)cl->buf[p.parity], (const TS*)cl->w,
                                  (const TS*)cl->f, 0, (TS*)cl->buf[1 - p.parity], cl->T, cl->Wp,
                                  cl->PT, cl->PL, cl->frame, item.y & 0xffff, item.y >> 16, item.z,
                                  item.w, gs, gt, p.alpha, lds, syy, syx);
