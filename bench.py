@@ -295,13 +295,19 @@ def bench_warmstart(args):
     S = torch.from_numpy(full_clip(1)).cuda()
     net = UNet((T, H, W))
     net.set_params(load_params(WEIGHTS))
+    plan, plan_info = None, None
+    if args.autotune:  # both solves use the plan the full workload is tuned to
+        from paper_1907_02731_amd.solver import Solver
+        with Solver(S, **GRAPH) as sol:
+            plan_info = sol.autotune(steps=32, cache=args.plan_cache or None)
+        plan = (plan_info["shape"], plan_info["chunks"])
     for _ in range(args.warmup):
-        solve_cold(S, tol=args.tol, graph=GRAPH)
-        solve_warm(S, net, tol=args.tol, graph=GRAPH)
+        solve_cold(S, tol=args.tol, graph=GRAPH, plan=plan)
+        solve_warm(S, net, tol=args.tol, graph=GRAPH, plan=plan)
     cold, warm = [], []
     for _ in range(args.steps):
-        cold.append(solve_cold(S, tol=args.tol, graph=GRAPH))
-        warm.append(solve_warm(S, net, tol=args.tol, graph=GRAPH))
+        cold.append(solve_cold(S, tol=args.tol, graph=GRAPH, plan=plan))
+        warm.append(solve_warm(S, net, tol=args.tol, graph=GRAPH, plan=plan))
     net.close()
     tc = float(np.median([c[2] for c in cold]))
     tw = float(np.median([w[2] for w in warm]))
@@ -322,6 +328,7 @@ def bench_warmstart(args):
         "warm": {"steps": rw.iters, "seconds": tw, "inference_seconds": ti},
         "speedup": tc / tw,
         "steps_saved": rc.iters - rw.iters,
+        "autotune": plan_info,
         "same_eigenvector": {"lambda_rel_diff": abs(rw.lam - rc.lam) / rc.lam,
                              "x_l2_diff": float(torch.linalg.norm(warm[-1][1] - cold[-1][1]))},
     }

@@ -259,11 +259,15 @@ def load_params(path: str = WEIGHTS) -> np.ndarray:
     return np.load(path, allow_pickle=False)
 
 
-def solve_cold(S: torch.Tensor, tol: float = 1e-5, graph: Dict = GRAPH, max_iters: int = 20000):
-    """Plain method from S: (result, eigenvector, seconds)."""
+def solve_cold(S: torch.Tensor, tol: float = 1e-5, graph: Dict = GRAPH, max_iters: int = 20000,
+               plan: Optional[Tuple[int, int]] = None):
+    """Plain method from S: (result, eigenvector, seconds).  `plan` = (block
+    shape, frame runs per tile) for the step kernel, else the default."""
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     with Solver(S, **graph) as sol:
+        if plan is not None:
+            sol.set_plan(*plan)
         r = sol.iterate(max_iters=max_iters, tol=tol)
         x = sol.eigvec()
     torch.cuda.synchronize()
@@ -271,7 +275,7 @@ def solve_cold(S: torch.Tensor, tol: float = 1e-5, graph: Dict = GRAPH, max_iter
 
 
 def solve_warm(S: torch.Tensor, net: UNet, tol: float = 1e-5, graph: Dict = GRAPH,
-               max_iters: int = 20000):
+               max_iters: int = 20000, plan: Optional[Tuple[int, int]] = None):
     """Network estimate as the start vector, then the plain method to the same
     tolerance: (result, eigenvector, seconds, seconds of inference)."""
     torch.cuda.synchronize()
@@ -280,6 +284,8 @@ def solve_warm(S: torch.Tensor, net: UNet, tol: float = 1e-5, graph: Dict = GRAP
     torch.cuda.synchronize()
     t_inf = time.perf_counter() - t0
     with Solver(S, **graph) as sol:
+        if plan is not None:
+            sol.set_plan(*plan)
         r = sol.iterate(x0, max_iters=max_iters, tol=tol)
         x = sol.eigvec()
     torch.cuda.synchronize()
