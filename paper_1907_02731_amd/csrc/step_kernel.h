@@ -157,7 +157,14 @@ struct Stor<__bf16> {
 template <>
 struct Stor<_Float16> {
     static __device__ __forceinline__ float ld(const _Float16* p, int64_t i) { return (float)p[i]; }
-    static __device__ __forceinline__ float rnd(float v) { return (float)(_Float16)v; }
+    // The float32 value is rounded: the empty asm keeps the compiler from
+    // fusing the product that produced v with this rounding (one rounding
+    // of the exact product instead of two), which it does or not depending
+    // on the surrounding code.
+    static __device__ __forceinline__ float rnd(float v) {
+        asm volatile("" : "+v"(v));
+        return (float)(_Float16)v;
+    }
     static __device__ __forceinline__ void st(_Float16* p, int64_t i, float v) { p[i] = (_Float16)v; }
     static __device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, int off) {
         const unsigned short h = __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0);
@@ -357,10 +364,8 @@ using ShapeDeep2 = Shape<2, 2>;
 //      own x, w, F, rounds to the storage type and reduces.
 // The raw region of the next frame is loaded straight into LDS while the X
 // phase runs: the Y phase is its only reader and has finished.
-// OWN_MAX: the LDS bytes a block may reach with the own-value ring in LDS
-// (see OWN_LDS); beyond it the ring is kept in registers.
 constexpr int kLdsThreeBlocks = 53 * 1024;  // three blocks share a CU's 160 KB
-template <typename TS, int RS, int RT, typename SH, int OWN_MAX>
+template <typename TS, int RS, int RT, typename SH>
 struct Geom {
     static constexpr int NT = SH::NT, PX = SH::PX, NSEG = SH::NSEG, NWAVES = SH::NWAVES;
     static constexpr int NF = SH::NF;                // pairwise feature channels
@@ -385,21 +390,14 @@ struct Geom {
     static constexpr int MP = TX - PX + XWA + (PX == 2 ? 2 : 0);  // y-filtered row pitch
     static constexpr int NR = 2 * RT + 1;            // frames in the register ring
     // The tile's own x, w, F of the last r_t + 1 frames (taken from the
-    // region while it is in LDS) are kept in an LDS ring when the block stays
-    // within OWN_MAX bytes, otherwise in registers (NARR * PX more per frame
-    // of the ring).
+    // region while it is in LDS) ride in a register shift ring.
     static constexpr int RT1 = RT + 1;                // frames in the own-value ring
     static constexpr int LDS_BASE = NARR * RAWE * ES + NFLD * TY * MP * 4;
-    static constexpr int LDS_OWN = RT1 * NARR * TY * TX * ES;
-    static constexpr bool OWN_LDS = LDS_BASE + LDS_OWN <= OWN_MAX;
-    static constexpr int LDS_TOT = LDS_BASE + (OWN_LDS ? LDS_OWN : 0);
     // Waves per SIMD the register budget is set for (the second launch-bounds
     // argument): three when three blocks fit the LDS and the register ring is
-    // small enough; otherwise two blocks share a CU (two waves per SIMD for
-    // 256-thread blocks).
+    // small enough; otherwise two (two blocks share a CU).
     static constexpr int RING = NR * NFLD * PX;
-    static constexpr int MINW =
-        LDS_TOT <= kLdsThreeBlocks && RING <= 84 ? 3 : (OWN_LDS ? 2 * NT / 256 : 2);
+    static constexpr int MINW = LDS_BASE <= kLdsThreeBlocks && RING <= 84 ? 3 : 2;
     static_assert(NS >= 1 && NS * EXT <= 64 && NS + 1 <= NWAVES, "y-pass lane mapping");
     static_assert(NS * PY >= TY && PY <= TY, "segments cover the tile rows");
     static_assert(MP % 4 == 0, "aligned rows");
@@ -408,12 +406,11 @@ struct Geom {
 
 // LDS of one block: the raw x, w, F of the tile plus halo for one frame
 // (filled by direct-to-LDS loads) and the y-filtered fields.
-template <typename TS, int RS, int RT, typename SH, int OWN_MAX>
+template <typename TS, int RS, int RT, typename SH>
 struct StepLds {
-    using G = Geom<TS, RS, RT, SH, OWN_MAX>;
+    using G = Geom<TS, RS, RT, SH>;
     TS raw[G::NARR][G::RAWE] __attribute__((aligned(16)));
     float mid3[G::NFLD][TY * G::MP] __attribute__((aligned(16)));
-    TS own[G::OWN_LDS ? G::RT1 : 1][G::NARR][G::OWN_LDS ? TY * TX : 4] __attribute__((aligned(16)));
 };
 
 // One work item: the 64 x 16 tile at picture origin (tx0, ty0) of one clip,
@@ -427,15 +424,15 @@ struct StepLds {
 // t + 1 (16 bytes per lane straight into LDS) issued one array per field; t
 // filter, combine with the own x, w, F of frame t - r_t, and reduce.  A frame
 // outside the clip skips the Y and X phases and clears its ring slot.
-template <typename TS, int RS, int RT, typename SH, int OWN_MAX>
+template <typename TS, int RS, int RT, typename SH>
 __device__ __forceinline__ void run_item(const TS* __restrict__ X, const TS* __restrict__ Wt,
                                          const TS* __restrict__ Fv, int64_t fstride,
                                          TS* __restrict__ Y, int T, int Wp, int PT, int PL,
                                          int64_t frame, int tx0, int ty0, int ta, int tb,
                                          const float* gs, const float* gt, float alpha,
-                                         StepLds<TS, RS, RT, SH, OWN_MAX>& lds, double& syy,
+                                         StepLds<TS, RS, RT, SH>& lds, double& syy,
                                          double& syx) {
-    using G = Geom<TS, RS, RT, SH, OWN_MAX>;
+    using G = Geom<TS, RS, RT, SH>;
     constexpr int NT = G::NT, PX = G::PX, NSEG = G::NSEG, IW = G::IW, EXT = G::EXT,
                   NS = G::NS, PY = G::PY, YW = G::YW, XWA = G::XWA, MP = G::MP, NR = G::NR,
                   RSA = G::RSA, IWA = G::IWA, CPR = G::CPR, NCH = G::NCH, NDMA = G::NDMA,
@@ -496,40 +493,11 @@ __device__ __forceinline__ void run_item(const TS* __restrict__ X, const TS* __r
     const int ooff = ((ty0 + PT + orow) * Wp + (tx0 + PL + ocol)) * ES;
 
     // Own x, w, F of this thread's PX pixels: copied from the region while
-    // the frame is in LDS, into the LDS own ring or, without it, into a
-    // register shift ring of r_t + 1 frames (oR[0] is the output frame's).
+    // the frame is in LDS into a register shift ring of r_t + 1 frames
+    // (oR[0] is the output frame's).
     const int rown = (orow + RS) * IWA + RSA + ocol;  // own pixels inside the region
-    const int town = orow * TX + ocol;                // own pixels inside the tile
-    auto save_own = [&](int t) {
-        if constexpr (G::OWN_LDS) {
-            const int slot = t % G::RT1;
-#pragma unroll
-            for (int a = 0; a < NARR; ++a) {
-                if constexpr (PX * ES == 16) {
-                    *reinterpret_cast<u32x4*>(&lds.own[slot][a][town]) =
-                        *reinterpret_cast<const u32x4*>(&lds.raw[a][rown]);
-                } else if constexpr (PX * ES == 8) {
-                    *reinterpret_cast<u32x2*>(&lds.own[slot][a][town]) =
-                        *reinterpret_cast<const u32x2*>(&lds.raw[a][rown]);
-                } else {
-                    *reinterpret_cast<uint32_t*>(&lds.own[slot][a][town]) =
-                        *reinterpret_cast<const uint32_t*>(&lds.raw[a][rown]);
-                }
-            }
-        }
-    };
     float qX[PX], qW[PX], qF[NF][PX];  // own x, w, F_c of the output frame
-    float oR[G::OWN_LDS ? 1 : G::RT1][NARR][PX];  // register own ring (no LDS ring)
-    auto read_own = [&](int t) {
-        const int slot = t % G::RT1;
-#pragma unroll
-        for (int i = 0; i < PX; ++i) {
-            qX[i] = (float)lds.own[slot][0][town + i];
-            qW[i] = (float)lds.own[slot][1][town + i];
-#pragma unroll
-            for (int c = 0; c < NF; ++c) qF[c][i] = (float)lds.own[slot][2 + c][town + i];
-        }
-    };
+    float oR[G::RT1][NARR][PX];  // own x, w, F_c of frames t_in - r_t .. t_in
 
     float ring[NR][NFLD][PX];  // x/y-filtered fields of the last NR frames
 #pragma unroll
@@ -563,20 +531,19 @@ __device__ __forceinline__ void run_item(const TS* __restrict__ X, const TS* __r
             }
             const int t_out = t_in - RT;
             const bool emit = t_out >= ta && t_out < tb;
-            if (t_in >= ta && t_in < tb) save_own(t_in);
-            if constexpr (!G::OWN_LDS) {
+            // shift the own-value ring down one frame; frame t_in's own values
+            // (needed only if it is an output frame) come from the region
 #pragma unroll
-                for (int q = 0; q < RT; ++q)
+            for (int q = 0; q < RT; ++q)
 #pragma unroll
-                    for (int ar = 0; ar < NARR; ++ar)
+                for (int ar = 0; ar < NARR; ++ar)
 #pragma unroll
-                        for (int i = 0; i < PX; ++i) oR[q][ar][i] = oR[q + 1][ar][i];
-                if (t_in >= ta && t_in < tb) {
+                    for (int i = 0; i < PX; ++i) oR[q][ar][i] = oR[q + 1][ar][i];
+            if (t_in >= ta && t_in < tb) {
 #pragma unroll
-                    for (int ar = 0; ar < NARR; ++ar)
+                for (int ar = 0; ar < NARR; ++ar)
 #pragma unroll
-                        for (int i = 0; i < PX; ++i) oR[RT][ar][i] = (float)lds.raw[ar][rown + i];
-                }
+                    for (int i = 0; i < PX; ++i) oR[RT][ar][i] = (float)lds.raw[ar][rown + i];
             }
             // A frame outside the clip is all zeros, and so are its filtered
             // fields: its ring slot is cleared instead of running the y and x
@@ -672,16 +639,12 @@ __device__ __forceinline__ void run_item(const TS* __restrict__ X, const TS* __r
             }
             // ---- filter along t, combine (Eq. (7)), reduce frame t_out ----
             if (emit) {
-                if constexpr (G::OWN_LDS) {
-                    read_own(t_out);
-                } else {
 #pragma unroll
-                    for (int i = 0; i < PX; ++i) {
-                        qX[i] = oR[0][0][i];
-                        qW[i] = oR[0][1][i];
+                for (int i = 0; i < PX; ++i) {
+                    qX[i] = oR[0][0][i];
+                    qW[i] = oR[0][1][i];
 #pragma unroll
-                        for (int c = 0; c < NF; ++c) qF[c][i] = oR[0][2 + c][i];
-                    }
+                    for (int c = 0; c < NF; ++c) qF[c][i] = oR[0][2 + c][i];
                 }
 #pragma unroll
                 for (int i = 0; i < PX; ++i) {
@@ -720,20 +683,13 @@ __device__ __forceinline__ void run_item(const TS* __restrict__ X, const TS* __r
     __syncthreads();  // the last region loads have landed before LDS is reused
 }
 
-// Both step kernels keep the own-value ring in LDS only where three blocks
-// still share a CU (16-bit storage); for float32 the LDS ring would leave
-// room for two blocks, so the own values ride in registers.  Three blocks
-// per CU let single-clip plans that cut each tile's frames into several runs
-// (more, shorter blocks) fill the chip and balance it, and give the batched
-// kernel's persistent grid 768 blocks instead of 512.
-constexpr int kStepOwnMax = kLdsThreeBlocks;
 
 template <typename TS, int RS, int RT, typename SH>
-__global__ __launch_bounds__(SH::NT, (Geom<TS, RS, RT, SH, kStepOwnMax>::MINW))
+__global__ __launch_bounds__(SH::NT, (Geom<TS, RS, RT, SH>::MINW))
 void step_kernel(StepParams p) {
-    using G = Geom<TS, RS, RT, SH, kStepOwnMax>;
+    using G = Geom<TS, RS, RT, SH>;
     constexpr int NT = G::NT, NR = G::NR;
-    __shared__ StepLds<TS, RS, RT, SH, kStepOwnMax> lds;
+    __shared__ StepLds<TS, RS, RT, SH> lds;
     __shared__ double fold_red[2][4];
 
     // Fold the previous step's partial sums (every block, same bits), record
@@ -757,7 +713,7 @@ void step_kernel(StepParams p) {
     const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
     const int4 item = p.items[lb];  // tile origin (picture coords) and frame range
     double syy = 0.0, syx = 0.0;
-    run_item<TS, RS, RT, SH, kStepOwnMax>((const TS*)p.x, (const TS*)p.w, (const TS*)p.f,
+    run_item<TS, RS, RT, SH>((const TS*)p.x, (const TS*)p.w, (const TS*)p.f,
                                            p.fstride, (TS*)p.y, p.T, p.Wp, p.PT, p.PL, p.frame,
                                            item.x, item.y, item.z, item.w, gs, gt, p.alpha, lds,
                                            syy, syx);
@@ -776,10 +732,10 @@ void step_kernel(StepParams p) {
 // slots in a fixed order, advances only that clip's state (so a converged
 // clip drops out of the next launch) and resets the queues.
 template <typename TS, int RS, int RT, typename SH>
-__global__ __launch_bounds__(SH::NT, (Geom<TS, RS, RT, SH, kStepOwnMax>::MINW)) void batch_step_kernel(BatchParams p) {
-    using G = Geom<TS, RS, RT, SH, kStepOwnMax>;
+__global__ __launch_bounds__(SH::NT, (Geom<TS, RS, RT, SH>::MINW)) void batch_step_kernel(BatchParams p) {
+    using G = Geom<TS, RS, RT, SH>;
     constexpr int NT = G::NT, NR = G::NR;
-    __shared__ StepLds<TS, RS, RT, SH, kStepOwnMax> lds;
+    __shared__ StepLds<TS, RS, RT, SH> lds;
     __shared__ int s_item;
 
     float gs[RS + 1];
@@ -831,7 +787,7 @@ __global__ __launch_bounds__(SH::NT, (Geom<TS, RS, RT, SH, kStepOwnMax>::MINW)) 
 #pragma unroll
         for (int m = 0; m < NR; ++m) gt[m] = p.gt[m < RT ? RT - m : m - RT] * c;
         double syy = 0.0, syx = 0.0;
-        run_item<TS, RS, RT, SH, kStepOwnMax>((const TS*)cl->buf[p.parity], (const TS*)cl->w,
+        run_item<TS, RS, RT, SH>((const TS*)cl->buf[p.parity], (const TS*)cl->w,
                                  (const TS*)cl->f, 0, (TS*)cl->buf[1 - p.parity], cl->T, cl->Wp,
                                  cl->PT, cl->PL, cl->frame, item.y & 0xffff, item.y >> 16, item.z,
                                  item.w, gs, gt, p.alpha, lds, syy, syx);
