@@ -47,21 +47,65 @@ def flops_per_voxel(r_s: int, r_t: int, nf: int = 1) -> int:
 
 def roofline(kernel: str, voxels: float, seconds: float, storage: str, r_s: int, r_t: int,
              traffic, nf: int = 1):
-    """Roofline entry of the step kernel: bound by VALU arithmetic (packed FP32
-    being unavailable, 176 flop per 16 bytes is above the 9.8 flop/B balance),
-    with the HBM view alongside."""
+    """Roofline entry of the step kernel against HBM bandwidth: algorithmic
+    bytes per launch (16 B per voxel in float32: read x, w, F, write y; 8 B in
+    16-bit storage; 4 B more per extra feature channel) over the average
+    launch duration, as a fraction of the 8 TB/s peak.  The VALU view sits
+    beside it: 176 flop per voxel (one channel, r_s = 5, r_t = 2) against the
+    FP32 vector peak without packed-FP32 instructions, which the library is
+    built without."""
     fl = flops_per_voxel(r_s, r_t, nf) * voxels
     by = (BYTES_PER_VOXEL[storage] + (nf - 1) * BYTES_PER_VOXEL[storage] // 4) * voxels
     tf = fl / seconds / 1e12
     gbs = by / seconds / 1e9
-    out = {"bound": "alu", "kernel": kernel, "achieved": tf, "peak": ALU_PEAK_TFLOPS,
-           "unit": "TFLOP/s", "frac": tf / ALU_PEAK_TFLOPS, "traffic": traffic,
-           "flops_per_launch": fl, "avg_launch_us": seconds * 1e6,
-           "frac_of_packed_peak": tf / ALU_PEAK_PACKED_TFLOPS,
-           "hbm": {"achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
-                   "bytes_per_launch": by,
-                   "measured": None if traffic is None else traffic / seconds / 1e9}}
-    return out
+    return {"bound": "hbm", "kernel": kernel, "achieved": gbs, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS, "traffic": traffic,
+            "bytes_per_launch": by, "avg_launch_us": seconds * 1e6,
+            "traffic_GBps": None if traffic is None else traffic / seconds / 1e9,
+            "alu": {"achieved": tf, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": tf / ALU_PEAK_TFLOPS, "flops_per_launch": fl,
+                    "frac_of_packed_peak": tf / ALU_PEAK_PACKED_TFLOPS}}
+
+
+def host_info() -> dict:
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "logical_cpus": os.cpu_count()}
+
+
+def copy_bandwidth(nbytes: int = 1 << 30, reps: int = 10) -> dict:
+    """Device-to-device copy of nbytes on the GPU (read + write counted),
+    timed with events, median of reps: the reachable HBM bandwidth beside
+    the vendor peak."""
+    import torch
+
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda:0").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1) / 1e3)
+    t = float(np.median(ts))
+    del a, b
+    return {"bytes": 2 * nbytes, "seconds": t, "GBps": 2 * nbytes / t / 1e9,
+            "frac_of_peak": 2 * nbytes / t / 1e9 / HBM_PEAK_GBS,
+            "what": f"torch copy of {nbytes >> 20} MiB on the device, read + write bytes, "
+                    f"median of {reps}"}
+
+
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_full_traffic.json")
 # Work plans the autotuner chose on this GPU, keyed by clip shape, radii,
 # storage and feature channels; reused so that repeated runs time the same plan.
@@ -135,12 +179,18 @@ def parse():
                     help="for 16-bit storage: error of the final iterate against the float32 "
                          "result after the same number of steps, and the FP64 oracle's residual "
                          "||Mx - lambda x|| / lambda for both")
+    ap.add_argument("--precision-oracle-steps", type=int, default=100,
+                    help="with --precision-report: steps after which the 16-bit and float32 "
+                         "iterates are compared with the FP64 oracle's (0 to skip)")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="run plain torch copies of 4*T*H*W bytes first (to scale the HBM "
                          "byte counters of a profiling run)")
     ap.add_argument("--features", type=int, default=1, choices=[1, 2],
                     help="pairwise feature channels (2: the clip and a motion-like map, Eq. (9))")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="full workload: skip the batched and warm-start time-to-converge "
+                         "measurements that the default line carries beside the plain one")
     ap.add_argument("--cpu-steps", type=int, default=20,
                     help="oracle power-iteration steps timed for the CPU baseline")
     return ap.parse_args()
@@ -157,24 +207,30 @@ def cpu_baseline(S, cfg_o, steps, Fs=None):
     power_iteration(lambda v: sum(m.apply(v) for m in mfs), x0, steps, 0.0)
     dt = time.perf_counter() - t0
     return {"value": S.size * steps / dt, "unit": "voxel-iterations/s", "cores": num_threads(),
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": host_info()["cpu_model"],
             "sample": f"{steps} FP64 power-iteration steps of the matrix-free oracle on the "
                       f"whole {'x'.join(map(str, S.shape))} clip ({dt:.1f} s)"}
 
 
-def precision_report(S, St, kw, K, x_lo):
+def precision_report(S, St, kw, K, x_lo, oracle_steps: int = 100):
     """Error of a 16-bit-storage iterate: against float32 storage after the same
-    K steps, and the FP64 oracle's relative residual of each vector."""
+    K steps, the FP64 oracle's relative residual of each vector, and -- after
+    ``oracle_steps`` steps from S -- the relative L2 and max-abs errors of the
+    16-bit and float32 iterates against the FP64 oracle's iterate (power
+    iteration over the matrix-free operator on the host's cores)."""
     import torch
 
-    from oracle import OracleConfig
+    from oracle import OracleConfig, power_iteration
     from oracle.native import MatrixFree
     from paper_1907_02731_amd.solver import Solver
 
-    kw32 = dict(kw, storage="f32")
-    with Solver(St, **kw32) as ref:
-        ref.iterate(max_iters=K, tol=0.0)
-        x32 = ref.eigvec().cpu().numpy().astype(np.float64).ravel()
+    def run(storage, k):
+        with Solver(St, **dict(kw, storage=storage)) as ref:
+            ref.autotune(steps=16, cache=PLAN_CACHE)
+            ref.iterate(max_iters=k, tol=0.0)
+            return ref.eigvec().cpu().numpy().astype(np.float64).ravel(), ref.plan()
+
+    x32, _ = run("f32", K)
     xl = x_lo.cpu().numpy().astype(np.float64).ravel()
     cfg = OracleConfig(r_t=kw["r_t"], r_s=kw["r_s"], sigma_t=kw["sigma_t"],
                        sigma_s=kw["sigma_s"], alpha=kw["alpha"], p=kw["p"])
@@ -187,21 +243,38 @@ def precision_report(S, St, kw, K, x_lo):
 
     r32, l32 = residual(x32)
     rlo, llo = residual(xl)
-    return {"storage": kw["storage"], "steps": K,
-            "rel_l2_vs_f32": float(np.linalg.norm(xl - x32) / np.linalg.norm(x32)),
-            "max_abs_vs_f32": float(np.max(np.abs(xl - x32))),
-            "oracle_residual_f32": r32, "oracle_residual": rlo,
-            "oracle_rayleigh_f32": l32, "oracle_rayleigh": llo}
+    out = {"storage": kw["storage"], "steps": K,
+           "rel_l2_vs_f32": float(np.linalg.norm(xl - x32) / np.linalg.norm(x32)),
+           "max_abs_vs_f32": float(np.max(np.abs(xl - x32))),
+           "oracle_residual_f32": r32, "oracle_residual": rlo,
+           "oracle_rayleigh_f32": l32, "oracle_rayleigh": llo}
+    if oracle_steps > 0:
+        t0 = time.perf_counter()
+        ref = power_iteration(mf.apply, S.astype(np.float64).ravel(), oracle_steps, 0.0)
+        t_or = time.perf_counter() - t0
+        xo = ref["x"]
+        cmp = {"steps": oracle_steps, "oracle_seconds": t_or}
+        for name in (kw["storage"], "f32"):
+            xg, plan = run(name, oracle_steps)
+            cmp[name] = {"rel_l2": float(np.linalg.norm(xg - xo) / np.linalg.norm(xo)),
+                         "max_abs": float(np.max(np.abs(xg - xo))), "plan": plan}
+        cmp["max_abs_x"] = float(np.max(np.abs(xo)))
+        out["vs_fp64_oracle"] = cmp
+    return out
 
 
-def bench_batch(args):
-    """Batched form: all clips iterated to tol by one persistent launch per
-    step, against the same clips solved one after another (plain)."""
+def batch_measure(args, storage: str = "f32", reps: int = None, warmup: int = None) -> dict:
+    """The batched form on the 24-clip ragged workload: every clip iterated
+    to the tolerance by one persistent launch per step, against the same
+    clips solved one after another by the plain method (contexts made outside
+    the timed regions).  Inputs resident in HBM."""
     import torch
 
     from paper_1907_02731_amd.solver import BatchSolver, Solver
     from paper_1907_02731_amd.synth import full_clip, ragged_shapes
 
+    reps = args.steps if reps is None else reps
+    warmup = args.warmup if warmup is None else warmup
     T1, H1, W1, r_t, r_s, s_t, s_s, _ = WORKLOADS["full"]
     shapes = ragged_shapes(args.clips, seed=3)
     dev = torch.device("cuda:0")
@@ -210,7 +283,7 @@ def bench_batch(args):
     torch.cuda.synchronize()
     N = sum(T * H * W for T, H, W in shapes)
     kw = dict(r_t=r_t, r_s=r_s, sigma_t=s_t, sigma_s=s_s, alpha=args.alpha, p=args.p,
-              storage=args.storage)
+              storage=storage)
     max_iters, tol = (args.iters, 0.0) if args.iters > 0 else (args.max_iters, args.tol)
     bs = BatchSolver(clips, **kw)
     plan_info = bs.autotune(steps=16, cache=args.plan_cache or None) if args.autotune else None
@@ -224,22 +297,24 @@ def bench_batch(args):
         bs.eigvecs()
         return r
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         batched()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(reps):
         res = batched()
     torch.cuda.synchronize()
-    t_batch = (time.perf_counter() - t0) / args.steps
+    t_batch = (time.perf_counter() - t0) / reps
     iters = [r.iters for r in res]
     vi = sum(T * H * W * k for (T, H, W), k in zip(shapes, iters))
     tm = bs.timing()
+    plan = bs.plan()
+    bs.close()
 
-    # plain: one context per clip, solved one after another (contexts made
-    # outside the timed region, as the batch's is)
     singles = [Solver(S, **kw) for S in clips]
     for s_ in singles:
+        if args.autotune:
+            s_.autotune(steps=16, cache=args.plan_cache or None)
         s_.iterate(max_iters=2, tol=0.0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -252,35 +327,48 @@ def bench_batch(args):
     t_plain = time.perf_counter() - t0
     for s_ in singles:
         s_.close()
+    del clips
+    torch.cuda.empty_cache()
+    return {"shapes": shapes, "voxels": N, "iters": iters, "plain_iters": plain_iters,
+            "voxel_iters": vi, "t_batch": t_batch, "t_plain": t_plain, "timing": tm,
+            "plan": plan, "autotune": plan_info, "r_s": r_s, "r_t": r_t, "s_s": s_s, "s_t": s_t}
+
+
+def bench_batch(args):
+    m = batch_measure(args, args.storage)
+    shapes, tm = m["shapes"], m["timing"]
     line = {
         "metric": "voxel-iterations/s (time to converge to 1e-5)",
-        "value": vi / t_batch,
+        "value": m["voxel_iters"] / m["t_batch"],
         "unit": "voxel-iterations/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": t_batch * 1e3,
+        "ms_per_step": m["t_batch"] * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": args.storage, "data": "synthetic",
-        "config": {"workload": f"batch: {len(shapes)} clips, {N} voxels, frames 20-100, "
-                               f"resolutions 240x427/360x640/480x854, r_s={r_s}, r_t={r_t}, "
-                               f"sigma_s={s_s}, sigma_t={s_t}, to delta<{args.tol:g}",
+        "config": {"workload": f"batch: {len(shapes)} clips, {m['voxels']} voxels, frames "
+                               f"20-100, resolutions 240x427/360x640/480x854, r_s={m['r_s']}, "
+                               f"r_t={m['r_t']}, sigma_s={m['s_s']}, sigma_t={m['s_t']}, to "
+                               f"delta<{args.tol:g}",
                    "clips": [list(s) for s in shapes]},
-        "plan": bs.plan(), "autotune": plan_info,
-        "iters_per_clip": iters,
-        "time_to_converge_ms": {"batched": t_batch * 1e3, "plain_sequential": t_plain * 1e3,
-                                "speedup": t_plain / t_batch},
-        "plain_iters_per_clip": plain_iters,
+        "plan": m["plan"], "autotune": m["autotune"],
+        "iters_per_clip": m["iters"],
+        "time_to_converge_ms": {"batched": m["t_batch"] * 1e3,
+                                "plain_sequential": m["t_plain"] * 1e3,
+                                "speedup": m["t_plain"] / m["t_batch"]},
+        "plain_iters_per_clip": m["plain_iters"],
         "batched_avg_launch_us": tm["loop_ms"] * 1e3 / max(tm["launches"], 1),
-        "roofline": roofline("batch_step_kernel (persistent, all clips)", vi / max(tm["iters"], 1),
-                             tm["loop_ms"] / 1e3 / max(tm["iters"], 1), args.storage, r_s, r_t, None),
+        "roofline": roofline("batch_step_kernel (persistent, all clips)",
+                             m["voxel_iters"] / max(tm["iters"], 1),
+                             tm["loop_ms"] / 1e3 / max(tm["iters"], 1), args.storage, m["r_s"],
+                             m["r_t"], None),
     }
-    bs.close()
     print(json.dumps(line), flush=True)
 
 
-def bench_warmstart(args):
+def warmstart_measure(args, reps: int = None, warmup: int = None, S_np=None) -> dict:
     """Learned warm start on the full-resolution clip: network inference, then
     the plain method from its estimate to the same tolerance, against the plain
-    method from S (cold start); both timed end to end, inputs in HBM."""
+    method from S (cold start); both end to end with the inputs in HBM."""
     import torch
 
     from paper_1907_02731_amd.synth import full_clip
@@ -288,11 +376,12 @@ def bench_warmstart(args):
                                                 solve_warm)
 
     if not os.path.exists(WEIGHTS):
-        print(f"bench.py: no trained weights at {WEIGHTS} (train them with "
-              "python -m paper_1907_02731_amd.train_warmstart)", file=sys.stderr)
-        sys.exit(2)
+        raise FileNotFoundError(f"no trained weights at {WEIGHTS} (train them with "
+                                "python -m paper_1907_02731_amd.train_warmstart)")
+    reps = args.steps if reps is None else reps
+    warmup = args.warmup if warmup is None else warmup
     T, H, W = 70, 480, 854
-    S = torch.from_numpy(full_clip(1)).cuda()
+    S = torch.from_numpy(full_clip(1) if S_np is None else S_np).cuda()
     net = UNet((T, H, W))
     net.set_params(load_params(WEIGHTS))
     plan, plan_info = None, None
@@ -301,11 +390,11 @@ def bench_warmstart(args):
         with Solver(S, **GRAPH) as sol:
             plan_info = sol.autotune(steps=32, cache=args.plan_cache or None)
         plan = (plan_info["shape"], plan_info["chunks"])
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         solve_cold(S, tol=args.tol, graph=GRAPH, plan=plan)
         solve_warm(S, net, tol=args.tol, graph=GRAPH, plan=plan)
     cold, warm = [], []
-    for _ in range(args.steps):
+    for _ in range(reps):
         cold.append(solve_cold(S, tol=args.tol, graph=GRAPH, plan=plan))
         warm.append(solve_warm(S, net, tol=args.tol, graph=GRAPH, plan=plan))
     net.close()
@@ -313,24 +402,36 @@ def bench_warmstart(args):
     tw = float(np.median([w[2] for w in warm]))
     ti = float(np.median([w[3] for w in warm]))
     rc, rw = cold[-1][0], warm[-1][0]
+    return {"shape": (T, H, W), "cold": {"steps": rc.iters, "seconds": tc, "lambda": rc.lam},
+            "warm": {"steps": rw.iters, "seconds": tw, "inference_seconds": ti,
+                     "lambda": rw.lam},
+            "speedup": tc / tw, "steps_saved": rc.iters - rw.iters, "autotune": plan_info,
+            "same_eigenvector": {"lambda_rel_diff": abs(rw.lam - rc.lam) / rc.lam,
+                                 "x_l2_diff": float(torch.linalg.norm(warm[-1][1] -
+                                                                      cold[-1][1]))}}
+
+
+def bench_warmstart(args):
+    try:
+        m = warmstart_measure(args)
+    except FileNotFoundError as e:
+        print(f"bench.py: {e}", file=sys.stderr)
+        sys.exit(2)
+    T, H, W = m["shape"]
     N = T * H * W
     line = {
         "metric": "time to converge to 1e-5, warm start (network + plain iterations) vs cold start",
-        "value": N * rc.iters / tw,
+        "value": N * m["cold"]["steps"] / m["warm"]["seconds"],
         "unit": "voxel-iterations/s (cold-start iterations per warm-start second)",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": tw * 1e3, "higher_is_better": True, "scaling": "weak",
+        "ms_per_step": m["warm"]["seconds"] * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32 (network bf16)", "data": "synthetic",
         "config": {"workload": "warmstart: one 70x480x854 clip (seed 1, held out from training), "
                                "r_s=5, r_t=2, sigma_s=2.0, sigma_t=1.0, alpha=1.0, p=0.2, tol 1e-5",
                    "T": T, "H": H, "W": W, "tol": args.tol},
-        "cold": {"steps": rc.iters, "seconds": tc},
-        "warm": {"steps": rw.iters, "seconds": tw, "inference_seconds": ti},
-        "speedup": tc / tw,
-        "steps_saved": rc.iters - rw.iters,
-        "autotune": plan_info,
-        "same_eigenvector": {"lambda_rel_diff": abs(rw.lam - rc.lam) / rc.lam,
-                             "x_l2_diff": float(torch.linalg.norm(warm[-1][1] - cold[-1][1]))},
+        "cold": m["cold"], "warm": m["warm"], "speedup": m["speedup"],
+        "steps_saved": m["steps_saved"], "autotune": m["autotune"],
+        "same_eigenvector": m["same_eigenvector"],
     }
     print(json.dumps(line), flush=True)
 
@@ -551,21 +652,47 @@ def main():
         "converged": bool(last.converged),
         "delta": last.delta,
         "lambda": last.lam,
-        "time_to_converge_ms": elapsed * 1e3 / args.steps,
+        "time_to_converge_ms": {"plain": elapsed * 1e3 / args.steps},
         "roofline": roofline("step_kernel (fused stencil + reductions)", N, avg_kernel_s,
                              args.storage, r_s, r_t,
                              measured_traffic(args.workload, args.storage, nf, sol.plan()),
                              nf=nf),
+        "host": host_info(),
     }
+    sol.close()
+    line["copy_bandwidth"] = copy_bandwidth()
+    if args.workload == "full" and args.storage == "f32" and nf == 1 and not args.no_forms \
+            and args.iters == 0:
+        # the other two forms of the metric, on the same GPU at the same tolerance
+        w = warmstart_measure(args, reps=3, warmup=1, S_np=S)
+        b = batch_measure(args, "f32", reps=2, warmup=1)
+        ttc = line["time_to_converge_ms"]
+        ttc["warm_start"] = w["warm"]["seconds"] * 1e3
+        ttc["warm_start_inference"] = w["warm"]["inference_seconds"] * 1e3
+        ttc["cold_start_same_run"] = w["cold"]["seconds"] * 1e3
+        ttc["warm_start_speedup"] = w["speedup"]
+        ttc["batched_24_clips"] = b["t_batch"] * 1e3
+        ttc["plain_24_clips_one_by_one"] = b["t_plain"] * 1e3
+        ttc["batched_speedup"] = b["t_plain"] / b["t_batch"]
+        line["forms"] = {
+            "warm_start": {"cold": w["cold"], "warm": w["warm"], "steps_saved": w["steps_saved"],
+                           "same_eigenvector": w["same_eigenvector"]},
+            "batched": {"clips": len(b["shapes"]), "voxels": b["voxels"],
+                        "iters_per_clip": b["iters"], "plain_iters_per_clip": b["plain_iters"],
+                        "plan": b["plan"],
+                        "voxel_iterations_per_s": b["voxel_iters"] / b["t_batch"],
+                        "avg_launch_us": b["timing"]["loop_ms"] * 1e3 /
+                        max(b["timing"]["launches"], 1)},
+        }
     if args.precision_report:
-        line["precision"] = precision_report(S, St, kw, max(iters), out)
+        line["precision"] = precision_report(S, St, kw, max(iters), out,
+                                              args.precision_oracle_steps)
     if not args.no_cpu_baseline:
         from oracle import OracleConfig
         cfg_o = OracleConfig(r_t=r_t, r_s=r_s, sigma_t=s_t, sigma_s=s_s, alpha=args.alpha,
                              p=args.p)
         line["cpu_baseline"] = cpu_baseline(S, cfg_o, args.cpu_steps if nf == 1 else
                                             max(1, args.cpu_steps // nf), Fs)
-    sol.close()
     print(json.dumps(line), flush=True)
 
 

@@ -57,6 +57,37 @@ def test_batch_trajectories_match_single_and_oracle(clips):
         assert np.linalg.norm(x - ref["x"]) <= 1e-5
 
 
+# Error budgets of the 16-bit storage forms against the FP64 oracle after 30
+# steps (relative L2): one rounding of w, F and every iterate to 8 (bfloat16)
+# or 11 (float16) significant bits.  The same bars as the single-clip form.
+BUDGET16 = {"bf16": 5e-2, "f16": 1e-2}
+
+
+@pytest.mark.parametrize("storage", ["bf16", "f16"])
+def test_batch_16bit_storage_matches_single_and_budget(clips, storage):
+    """The batched kernels with bfloat16 / float16 storage (own values of
+    the tile in the register ring, as in the float32 form): every clip
+    follows its single-clip trajectory, and stays within the storage error
+    budget of the FP64 oracle."""
+    K = 30
+    with BatchSolver([_t(S) for S, _ in clips], storage=storage, **KW) as bs:
+        res = bs.iterate(max_iters=K, tol=0.0)
+        xs = [x.cpu().numpy().astype(np.float64).ravel() for x in bs.eigvecs()]
+    for (S, M), r, x in zip(clips, res, xs):
+        assert r.iters == K
+        with Solver(_t(S), storage=storage, **KW) as sol:
+            r1 = sol.iterate(max_iters=K, tol=0.0)
+            x1 = sol.eigvec().cpu().numpy().astype(np.float64).ravel()
+        ref = power_iteration(lambda v: M @ v, S.astype(np.float64).ravel(), K, 0.0)
+        rel = np.linalg.norm(x - ref["x"]) / np.linalg.norm(ref["x"])
+        print(f"{storage} {S.shape}: ||x_batch - x_single|| = {np.linalg.norm(x - x1):.3e}, "
+              f"rel L2 vs oracle {rel:.3e}", flush=True)
+        assert np.linalg.norm(x - x1) <= 1e-6
+        assert abs(r.lam - r1.lam) <= 1e-9 * r1.lam
+        assert rel <= BUDGET16[storage]
+        assert np.all(x[S.ravel() == 0] == 0.0)
+
+
 def test_each_clip_stops_on_its_own(clips):
     tol = 1e-5
     with BatchSolver([_t(S) for S, _ in clips], **KW) as bs:

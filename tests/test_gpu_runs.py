@@ -10,7 +10,7 @@ the same order whatever the plan, so the outputs of all plans must agree bit
 for bit; the plan only changes which block computes a voxel.  Cases: runs
 shorter than a ring turn, runs that start or end inside the clip's zero
 padding, r_t from 1 to 4, both block shapes, float32 and bfloat16 storage
-(bfloat16 keeps the tile's own values in an LDS ring).
+(every storage type keeps the tile's own x, w, F in a register shift ring).
 """
 import numpy as np
 import pytest
