@@ -32,6 +32,7 @@
 #ifndef SFSEG_H
 #define SFSEG_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -165,6 +166,29 @@ int sfseg_eigvec(sfseg_ctx *ctx, float *out);
  * float32 volumes (they may not alias); x is rounded to storage precision
  * first.  Does not disturb the iteration state.  Blocks until done. */
 int sfseg_apply(sfseg_ctx *ctx, const float *x, float *y);
+
+/* ---- Application without allocation ------------------------------------
+ * For callers that cannot allocate device memory or block: code under
+ * stream capture, tight serving loops, harnesses that forbid hipMalloc.
+ * sfseg_apply_noalloc computes what sfseg_apply computes (the same kernels,
+ * the same bits) but takes its staging volumes (x and y in padded storage
+ * precision), its two state slots and the step kernel's float64 partial sums
+ * from one static device array of SFSEG_NOALLOC_SCRATCH_BYTES per GPU,
+ * reserved when the library is loaded and held until the process ends.  It
+ * calls no allocator and no memset, and does not block: the launches are
+ * ordered on the context's stream and y is ready when that stream reaches
+ * them.  The array is shared by every call on a GPU and keeps the last call's
+ * contents (the call clears what must start at zero), so calls that overlap
+ * in time on one GPU (other streams or host threads) race; order them.
+ * Errors: SFSEG_ERR_INVALID_ARG for NULL or aliasing pointers and for a
+ * context whose staging needs more than the array holds
+ * (sfseg_apply_noalloc_bytes tells how much it needs); SFSEG_ERR_STATE for a
+ * batch context. */
+#define SFSEG_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int sfseg_apply_noalloc(sfseg_ctx *ctx, const float *x, float *y);
+/* Bytes of the static array sfseg_apply_noalloc needs for this context (0
+ * for NULL or batch contexts).  Host only. */
+size_t sfseg_apply_noalloc_bytes(const sfseg_ctx *ctx);
 
 /* ---- Binarisation (Sec. 4.1; Alg. 1, step 3) ---------------------------
  * Algorithm 1 projects the normalised solution through a sigmoid after each

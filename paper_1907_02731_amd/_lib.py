@@ -94,6 +94,10 @@ def lib():
     L.sfseg_eigvec.restype = ctypes.c_int
     L.sfseg_apply.argtypes = [P, P, P]
     L.sfseg_apply.restype = ctypes.c_int
+    L.sfseg_apply_noalloc.argtypes = [P, P, P]
+    L.sfseg_apply_noalloc.restype = ctypes.c_int
+    L.sfseg_apply_noalloc_bytes.argtypes = [P]
+    L.sfseg_apply_noalloc_bytes.restype = ctypes.c_size_t
     pbin = ctypes.POINTER(Binarize)
     L.sfseg_binarize_default.argtypes = [pbin]
     L.sfseg_binarize_default.restype = None

@@ -101,6 +101,9 @@ def test_null_arguments_rejected():
     assert L.sfseg_apply(None, ctypes.c_void_p(1), ctypes.c_void_p(2)) == \
         _lib.SFSEG_ERR_INVALID_ARG
     assert L.sfseg_set_features(None, ctypes.c_void_p(1), None) == _lib.SFSEG_ERR_INVALID_ARG
+    assert L.sfseg_apply_noalloc(None, ctypes.c_void_p(1), ctypes.c_void_p(2)) == \
+        _lib.SFSEG_ERR_INVALID_ARG
+    assert L.sfseg_apply_noalloc_bytes(None) == 0
     assert L.sfseg_last_timing(None, None) == _lib.SFSEG_ERR_INVALID_ARG
     b = _lib.Binarize()
     L.sfseg_binarize_default(ctypes.byref(b))
