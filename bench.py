@@ -407,8 +407,9 @@ def warmstart_measure(args, reps: int = None, warmup: int = None, S_np=None) -> 
                      "lambda": rw.lam},
             "speedup": tc / tw, "steps_saved": rc.iters - rw.iters, "autotune": plan_info,
             "same_eigenvector": {"lambda_rel_diff": abs(rw.lam - rc.lam) / rc.lam,
-                                 "x_l2_diff": float(torch.linalg.norm(warm[-1][1] -
-                                                                      cold[-1][1]))}}
+                                 "x_l2_diff": float(np.linalg.norm(
+                                     warm[-1][1].cpu().numpy().astype(np.float64) -
+                                     cold[-1][1].cpu().numpy().astype(np.float64)))}}
 
 
 def bench_warmstart(args):

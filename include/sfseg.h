@@ -167,6 +167,23 @@ int sfseg_eigvec(sfseg_ctx *ctx, float *out);
  * first.  Does not disturb the iteration state.  Blocks until done. */
 int sfseg_apply(sfseg_ctx *ctx, const float *x, float *y);
 
+/* Training loss of the learned warm start on the error that survives k
+ * power-iteration steps (Algorithm 1 iterates Eq. (4) with the normalisation
+ * of Eq. (8) from the start vector; the warm start supplies that vector):
+ *     v = M^k xhat,  *loss = 1 - cos(v, target),
+ *     grad = dL/dxhat = M^k dL/dv  (M of Eq. (2) is symmetric),
+ *     dL/dv = -(target / (|v| |target|) - cos v / |v|^2).
+ * xhat, target and grad are device float32 T*H*W volumes of the context's
+ * clip (grad may not alias the others); 0 <= k <= 4096 (k = 0 is the plain
+ * cosine loss).  The 2k products use the context's step kernel and plan;
+ * every product's result is divided by its float64 norm, and the loss's sums
+ * are float64.  Allocates a work volume and k norms on the first call (kept
+ * until sfseg_destroy); blocks until grad is written.  *loss (host) may be
+ * NULL.  Errors: SFSEG_ERR_ZERO_NORM if M^k xhat or target is zero,
+ * SFSEG_ERR_NONFINITE on overflow, SFSEG_ERR_STATE for a batch context. */
+int sfseg_spectral_grad(sfseg_ctx *ctx, const float *xhat, const float *target, int32_t k,
+                        float *grad, double *loss);
+
 /* ---- Application without allocation ------------------------------------
  * For callers that cannot allocate device memory or block: code under
  * stream capture, tight serving loops, harnesses that forbid hipMalloc.

@@ -40,7 +40,7 @@ import numpy as np
 
 __all__ = ["LAYERS", "param_count", "init_params", "pack", "unpack", "conv3", "conv3_backward",
            "pool2", "pool2_backward", "up2", "up2_backward", "forward", "backward",
-           "cosine_loss"]
+           "cosine_loss", "spectral_cosine_loss"]
 
 # (name, Cin, Cout, kernel size)
 LAYERS: List[Tuple[str, int, int, int]] = [
@@ -165,6 +165,29 @@ def cosine_loss(xh: np.ndarray, target: np.ndarray):
     c = float(a @ t) / (na * nt)
     g = -(t / (na * nt) - c * a / (na * na))
     return 1.0 - c, g.reshape(xh.shape)
+
+
+def spectral_cosine_loss(apply, xh: np.ndarray, target: np.ndarray, k: int):
+    """Loss on the error that survives k power-iteration steps, and its
+    gradient with respect to the start vector xh:
+
+        v = M^k xh,   L = 1 - cos(v, target),
+        dL/dxh = (M^k)^T dL/dv = M^k dL/dv          (M of Eq. (2) is symmetric)
+
+    ``apply(x)`` returns M x for a flat float64 vector.  Power iteration
+    (Eq. (4), Eq. (8)) from xh reaches the direction of v after k steps, so L
+    measures what k steps leave of the start vector's error.  v is formed by
+    k products and normalised once at the end (the loss does not depend on its
+    scale); the gradient is dL/dv pushed back through the k products."""
+    x = np.asarray(xh, dtype=np.float64).ravel()
+    v = x.copy()
+    for _ in range(k):
+        v = apply(v)
+    loss, gv = cosine_loss(v, target)
+    g = gv.ravel()
+    for _ in range(k):
+        g = apply(g)
+    return loss, g.reshape(np.shape(xh))
 
 
 def _relu(v):

@@ -94,6 +94,8 @@ def lib():
     L.sfseg_eigvec.restype = ctypes.c_int
     L.sfseg_apply.argtypes = [P, P, P]
     L.sfseg_apply.restype = ctypes.c_int
+    L.sfseg_spectral_grad.argtypes = [P, P, P, ctypes.c_int32, P, ctypes.POINTER(ctypes.c_double)]
+    L.sfseg_spectral_grad.restype = ctypes.c_int
     L.sfseg_apply_noalloc.argtypes = [P, P, P]
     L.sfseg_apply_noalloc.restype = ctypes.c_int
     L.sfseg_apply_noalloc_bytes.argtypes = [P]

@@ -17,7 +17,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsfseg.so")
 SOURCES = ["step_f32.hip", "step_bf16.hip", "step_f16.hip", "kernels.hip", "api.hip",
-           "batch.hip", "unet.hip", "binarize.hip", "noalloc.hip"]
+           "batch.hip", "unet.hip", "binarize.hip", "noalloc.hip",
+           "spectral.hip"]
 ARCH = os.environ.get("SFSEG_OFFLOAD_ARCH", "gfx950")
 
 

@@ -104,11 +104,12 @@ void sfseg_destroy(sfseg_ctx* ctx) {
         if (e) (void)hipEventDestroy(e);
     void* dev[] = {ctx->w, ctx->f, ctx->s0, ctx->buf[0], ctx->buf[1], ctx->apply_in,
                    ctx->apply_out, ctx->st, ctx->st_apply, ctx->d_bad, ctx->partials,
-                   ctx->step_part, ctx->items};
+                   ctx->step_part, ctx->items, ctx->spec_buf, ctx->spec_norms, ctx->spec_part};
     for (void* p : dev)
         if (p) (void)hipFree(p);
     if (ctx->h_st) (void)hipHostFree(ctx->h_st);
     if (ctx->h_bad) (void)hipHostFree(ctx->h_bad);
+    if (ctx->h_spec) (void)hipHostFree(ctx->h_spec);
     delete ctx;
 }
 
@@ -511,6 +512,18 @@ int sfseg_apply(sfseg_ctx* ctx, const float* x, float* y) {
     if (ctx->batch) return fail(SFSEG_ERR_STATE, "batch context: sfseg_apply works on one clip");
     if (x == (const float*)y) return fail(SFSEG_ERR_INVALID_ARG, "x and y may not alias");
     HIP_TRY(hipSetDevice(ctx->device));
+    if (int rc = sfseg_host::apply_async(ctx, x, y)) return rc;
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return SFSEG_OK;
+}
+
+}  // extern "C"
+
+namespace sfseg_host {
+
+// y = M x on the context's stream, through the staging volumes (allocated on
+// the first call); does not wait.
+int apply_async(sfseg_ctx* ctx, const float* x, float* y) {
     const size_t bytes = (size_t)ctx->L.total * dtype_size(ctx->cfg.storage);
     if (!ctx->apply_in) {
         HIP_TRY(hipMalloc(&ctx->apply_in, bytes));
@@ -541,9 +554,12 @@ int sfseg_apply(sfseg_ctx* ctx, const float* x, float* y) {
                                ctx->step_grid, ctx->stream));
     HIP_TRY(sfseg::launch_from_storage(ctx->cfg.storage, ctx->apply_out, y, ctx->L, ctx->ew_grid,
                                        ctx->stream));
-    HIP_TRY(hipStreamSynchronize(ctx->stream));
     return SFSEG_OK;
 }
+
+}  // namespace sfseg_host
+
+extern "C" {
 
 int sfseg_get_plan(const sfseg_ctx* ctx, sfseg_plan* out) {
     if (!ctx || !out) return fail(SFSEG_ERR_INVALID_ARG, "ctx or out is NULL");

@@ -51,6 +51,8 @@ int launch_steps(sfseg_ctx* ctx, int first_buf, int count);
 // step's output) and makes slot 0 current.
 int launch_finish(sfseg_ctx* ctx, int slot);
 int batch_set_plan(sfseg_ctx* ctx, int32_t shape, int32_t chunks);
+// y = M x on the context's stream (sfseg_apply without the final wait).
+int apply_async(sfseg_ctx* ctx, const float* x, float* y);
 }  // namespace sfseg_host
 
 struct sfseg_ctx {
@@ -90,4 +92,9 @@ struct sfseg_ctx {
     int cur = 0;  // buffer holding the current iterate
     sfseg_timing timing{};
     sfseg_host::BatchState* batch = nullptr;  // set for contexts made by sfseg_batch_create
+    float* spec_buf = nullptr;      // sfseg_spectral_grad: work volume (T*H*W float32)
+    double* spec_norms = nullptr;   // sfseg_spectral_grad: ||M y_i|| of the forward products
+    int spec_norms_cap = 0;
+    double* spec_part = nullptr;    // sfseg_spectral_grad: block sums
+    double* h_spec = nullptr;       // pinned copy of the loss sums
 };

@@ -143,6 +143,24 @@ class Solver:
             torch.cuda.current_stream().wait_stream(self.stream)
         return out
 
+    def spectral_grad(self, xhat: torch.Tensor, target: torch.Tensor, k: int,
+                      out: Optional[torch.Tensor] = None):
+        """Loss 1 - cos(M^k xhat, target) and its gradient with respect to
+        xhat (sfseg_spectral_grad): (grad, loss)."""
+        px = _dev_ptr(xhat, "xhat", self.shape)
+        pt = _dev_ptr(target, "target", self.shape)
+        with torch.cuda.device(self.device):
+            if out is None:
+                with torch.cuda.stream(self.stream):
+                    out = torch.empty(self.shape, dtype=torch.float32, device=self.device)
+            po = _dev_ptr(out, "out", self.shape)
+            self.stream.wait_stream(torch.cuda.current_stream())
+            loss = ctypes.c_double()
+            _lib.check(_lib.lib().sfseg_spectral_grad(self._handle(), px, pt, int(k), po,
+                                                      ctypes.byref(loss)), "sfseg_spectral_grad")
+            torch.cuda.current_stream().wait_stream(self.stream)
+        return out, float(loss.value)
+
     # -- binarisation (Sec. 4.1) ----------------------------------------------
     def _mask_out(self, out: Optional[torch.Tensor]) -> torch.Tensor:
         if out is None:

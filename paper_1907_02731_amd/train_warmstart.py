@@ -47,7 +47,8 @@ def evaluate(net: UNet, seeds, tol: float = 1e-5):
         row = {"seed": sd, "cold_steps": rc.iters, "warm_steps": rw.iters,
                "cold_s": tc, "warm_s": tw, "inference_s": ti,
                "lambda_rel_diff": abs(rw.lam - rc.lam) / rc.lam,
-               "x_diff": float(torch.linalg.norm(xw - xc))}
+               "x_diff": float(np.linalg.norm(xw.cpu().numpy().astype(np.float64) -
+                                              xc.cpu().numpy().astype(np.float64)))}
         log(json.dumps(row))
         rows.append(row)
         del S

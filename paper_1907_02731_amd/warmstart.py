@@ -211,39 +211,29 @@ def train_spectral(net: UNet, inputs: Sequence[torch.Tensor], targets: Sequence[
 
         L = 1 - cos(M^k x^, x*),   dL/dx^ = M^k dL/dy   (M is symmetric),
 
-    with M the clip's graph applied by the library (sfseg_apply).  Components
-    of x^ along fast-decaying eigenvectors are damped by (lambda_i /
-    lambda_1)^k before the loss sees them, so the network is trained on the
-    slow components, the ones that set the number of steps.  Intermediate
-    vectors are rescaled by their norms; the same scalars divide the backward
-    chain, so the gradient is exact."""
+    with M the clip's graph; the loss and dL/dx^ come from the library
+    (sfseg_spectral_grad).  Components of x^ along fast-decaying eigenvectors
+    are damped by (lambda_i / lambda_1)^k before the loss sees them, so the
+    network is trained on the slow components, the ones that set the number
+    of steps."""
     rng = np.random.Generator(np.random.PCG64(seed))
     total = epochs * len(inputs)
     losses: List[float] = []
     step = 0
     t0 = time.time()
+    g_buf = None
     with Solver(inputs[0], **graph) as sol:
         for _ in range(epochs):
             for i in rng.permutation(len(inputs)):
                 step += 1
                 rate = lr_final + 0.5 * (lr - lr_final) * (1 + math.cos(math.pi * (step - 1) / total))
                 sol.set_features(inputs[i])
-                y = net.forward(inputs[i])
-                scale = []
-                for _ in range(k):
-                    y = sol.apply(y)
-                    s_ = torch.linalg.norm(y)
-                    scale.append(s_)
-                    y = y / s_
-                t = targets[i]
-                ny, nt = torch.linalg.norm(y), torch.linalg.norm(t)
-                c = torch.dot(y.ravel(), t.ravel()) / (ny * nt)
-                g = -(t / (ny * nt) - c * y / (ny * ny))
-                for s_ in reversed(scale):
-                    g = sol.apply(g) / s_
+                xhat = net.forward(inputs[i])
+                g, loss = sol.spectral_grad(xhat, targets[i], k, out=g_buf)
+                g_buf = g
                 net.backward_from(g)
                 net.adam_step(rate, step)
-                losses.append(1.0 - float(c))
+                losses.append(loss)
                 if log and (step % log_every == 0 or step == total):
                     log(f"step {step}/{total} loss after {k} steps (mean of last {log_every}) "
                         f"{np.mean(losses[-log_every:]):.6f} rate {rate:.2e} {time.time() - t0:.1f}s")

@@ -104,6 +104,7 @@ def test_null_arguments_rejected():
     assert L.sfseg_apply_noalloc(None, ctypes.c_void_p(1), ctypes.c_void_p(2)) == \
         _lib.SFSEG_ERR_INVALID_ARG
     assert L.sfseg_apply_noalloc_bytes(None) == 0
+    assert L.sfseg_spectral_grad(None, None, None, 1, None, None) == _lib.SFSEG_ERR_INVALID_ARG
     assert L.sfseg_last_timing(None, None) == _lib.SFSEG_ERR_INVALID_ARG
     b = _lib.Binarize()
     L.sfseg_binarize_default(ctypes.byref(b))

@@ -158,3 +158,82 @@ def test_planted_backward_mistake_is_caught():
     lhs = np.sum(U.conv3(x, W, np.zeros(2)) * gy)
     assert abs(lhs - np.sum(gx * x)) <= 1e-10 * abs(lhs)
     assert abs(lhs - np.sum(gx_bad * x)) > 1e-3 * abs(lhs)
+
+
+# ---------------------------------------------------------------------------
+# Spectral training loss: L = 1 - cos(M^k x^, x*)
+# ---------------------------------------------------------------------------
+
+def _small_graph():
+    from oracle import OracleConfig, build_adjacency
+    r = _rng(21)
+    S = r.random((3, 6, 7))
+    S[S < 0.2] = 0.0
+    cfg = OracleConfig(r_t=1, r_s=2, sigma_t=1.0, sigma_s=1.5, alpha=1.0, p=0.2)
+    return S, build_adjacency(S, None, cfg)
+
+
+@pytest.mark.parametrize("k", [1, 3])
+def test_spectral_loss_gradient_matches_finite_differences(k):
+    S, M = _small_graph()
+    r = _rng(22)
+    xh = r.random(S.shape) + 0.1
+    target = r.random(S.shape)
+    loss, g = U.spectral_cosine_loss(lambda v: M @ v, xh, target, k)
+    for _ in range(5):
+        d = r.normal(size=S.shape)
+        h = 1e-6
+        lp = U.spectral_cosine_loss(lambda v: M @ v, xh + h * d, target, k)[0]
+        lm = U.spectral_cosine_loss(lambda v: M @ v, xh - h * d, target, k)[0]
+        fd = (lp - lm) / (2 * h)
+        assert abs(fd - np.sum(g * d)) <= 1e-6 * abs(fd) + 1e-9
+
+
+def test_spectral_loss_of_a_diagonal_operator_is_a_weighted_cosine():
+    # r_s = r_t = 0: M = diag(w^2) (Eq. (2) with only the self-loop), so
+    # M^k x = w^(2k) x element by element and the gradient is w^(2k) times the
+    # cosine-loss gradient at that vector -- written out by hand.
+    from oracle import OracleConfig, build_adjacency
+    r = _rng(23)
+    S = r.random((2, 4, 5)) + 0.1
+    cfg = OracleConfig(r_t=0, r_s=0, sigma_t=1.0, sigma_s=1.0, alpha=1.0, p=0.5)
+    M = build_adjacency(S, None, cfg)
+    d = (S ** 0.5).ravel() ** 2
+    xh, t = r.random(S.shape), r.random(S.shape)
+    k = 4
+    v = d ** k * xh.ravel()
+    nv, nt = np.linalg.norm(v), np.linalg.norm(t)
+    c = v @ t.ravel() / (nv * nt)
+    g = d ** k * -(t.ravel() / (nv * nt) - c * v / nv ** 2)
+    loss, gg = U.spectral_cosine_loss(lambda u: M @ u, xh, t, k)
+    assert abs(loss - (1.0 - c)) <= 1e-14
+    assert np.allclose(gg.ravel(), g, rtol=1e-12, atol=1e-15)
+
+
+def test_spectral_loss_at_the_eigenvector_is_zero_and_flat():
+    S, M = _small_graph()
+    lam, V = np.linalg.eigh(M.toarray())
+    v1 = np.abs(V[:, -1]).reshape(S.shape)
+    loss, g = U.spectral_cosine_loss(lambda v: M @ v, 2.0 * v1, v1, 5)
+    assert abs(loss) <= 1e-12
+    assert np.linalg.norm(g) <= 1e-9
+
+
+def test_planted_spectral_mistake_is_caught():
+    # one product too few on the way back breaks the finite-difference pin
+    S, M = _small_graph()
+    r = _rng(24)
+    xh, target = r.random(S.shape) + 0.1, r.random(S.shape)
+    k = 3
+    v = xh.ravel()
+    for _ in range(k):
+        v = M @ v
+    _, gv = U.cosine_loss(v, target.ravel())
+    g_bad = gv
+    for _ in range(k - 1):
+        g_bad = M @ g_bad
+    d = r.normal(size=S.shape)
+    h = 1e-6
+    fd = (U.spectral_cosine_loss(lambda u: M @ u, xh + h * d, target, k)[0]
+          - U.spectral_cosine_loss(lambda u: M @ u, xh - h * d, target, k)[0]) / (2 * h)
+    assert abs(fd - np.sum(g_bad * d.ravel())) > 1e-3 * abs(fd)
