@@ -576,6 +576,10 @@ int sfseg_set_plan(sfseg_ctx* ctx, int32_t shape, int32_t chunks) {
     if (ctx->batch) return batch_set_plan(ctx, shape, chunks);
     if (shape < 0 || shape >= sfseg::STEP_SHAPES)
         return fail(SFSEG_ERR_INVALID_ARG, "shape must be 0..%d", sfseg::STEP_SHAPES - 1);
+    if (!sfseg::shape_supported(shape, ctx->cfg.storage, ctx->nf, ctx->cfg.r_t, false))
+        return fail(SFSEG_ERR_UNSUPPORTED,
+                    "shape %d needs float32 storage, one feature channel and r_t <= %d", shape,
+                    sfseg::MFMA_MAX_RT);
     if (chunks < 1 || chunks > max_chunks(ctx->cfg))
         return fail(SFSEG_ERR_INVALID_ARG, "chunks must be 1..%d for this clip", max_chunks(ctx->cfg));
     HIP_TRY(hipSetDevice(ctx->device));

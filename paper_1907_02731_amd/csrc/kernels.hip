@@ -252,13 +252,21 @@ dim3 ew_dims(const Layout& L, int blocks) {
 
 }  // namespace
 
-// `shape` is a kernel shape (kernel_shape): 0..1 for every storage type,
-// 2..3 (two feature channels) for float32 only.
+// `shape` is a kernel variant (kernel_shape): 0..1 for every storage type,
+// 2 (matrix-core spatial passes, r_t <= 2) and 3..4 (two feature channels)
+// for float32 only.
+static bool variant_ok(int dtype, int shape, int rs, int rt) {
+    if (shape < 0 || shape >= KERNEL_VARIANTS || rs < 0 || rs > SFSEG_MAX_RS || rt < 0 ||
+        rt > SFSEG_MAX_RT)
+        return false;
+    if (shape >= 2 && dtype != SFSEG_F32) return false;
+    if (shape == SHAPE_MFMA && rt > MFMA_MAX_RT) return false;
+    return true;
+}
+
 hipError_t launch_step(int dtype, int shape, int rs, int rt, const StepParams& p, int grid,
                        hipStream_t s) {
-    if (shape < 0 || shape >= 2 * STEP_SHAPES || (shape >= STEP_SHAPES && dtype != SFSEG_F32) ||
-        rs < 0 || rs > SFSEG_MAX_RS || rt < 0 || rt > SFSEG_MAX_RT)
-        return hipErrorInvalidValue;
+    if (!variant_ok(dtype, shape, rs, rt)) return hipErrorInvalidValue;
     switch (dtype) {
         case SFSEG_F32: return launch_step_f32(shape, rs, rt, p, grid, s);
         case SFSEG_BF16: return launch_step_bf16(shape, rs, rt, p, grid, s);
@@ -269,7 +277,7 @@ hipError_t launch_step(int dtype, int shape, int rs, int rt, const StepParams& p
 
 hipError_t launch_batch_step(int dtype, int shape, int rs, int rt, const BatchParams& p, int grid,
                              hipStream_t s) {
-    if (shape < 0 || shape >= STEP_SHAPES || rs < 0 || rs > SFSEG_MAX_RS || rt < 0 ||
+    if (shape < 0 || shape >= 2 || rs < 0 || rs > SFSEG_MAX_RS || rt < 0 ||
         rt > SFSEG_MAX_RT)
         return hipErrorInvalidValue;
     switch (dtype) {
@@ -281,7 +289,7 @@ hipError_t launch_batch_step(int dtype, int shape, int rs, int rt, const BatchPa
 }
 
 hipError_t batch_max_blocks_per_cu(int dtype, int shape, int rs, int rt, int* blocks) {
-    if (shape < 0 || shape >= STEP_SHAPES || rs < 0 || rs > SFSEG_MAX_RS || rt < 0 ||
+    if (shape < 0 || shape >= 2 || rs < 0 || rs > SFSEG_MAX_RS || rt < 0 ||
         rt > SFSEG_MAX_RT)
         return hipErrorInvalidValue;
     switch (dtype) {
@@ -293,9 +301,7 @@ hipError_t batch_max_blocks_per_cu(int dtype, int shape, int rs, int rt, int* bl
 }
 
 hipError_t step_max_blocks_per_cu(int dtype, int shape, int rs, int rt, int* blocks) {
-    if (shape < 0 || shape >= 2 * STEP_SHAPES || (shape >= STEP_SHAPES && dtype != SFSEG_F32) ||
-        rs < 0 || rs > SFSEG_MAX_RS || rt < 0 || rt > SFSEG_MAX_RT)
-        return hipErrorInvalidValue;
+    if (!variant_ok(dtype, shape, rs, rt)) return hipErrorInvalidValue;
     switch (dtype) {
         case SFSEG_F32: return occ_step_f32(shape, rs, rt, blocks);
         case SFSEG_BF16: return occ_step_bf16(shape, rs, rt, blocks);

@@ -101,12 +101,23 @@ struct BatchParams {
 constexpr int TILE_X = 64;
 constexpr int TILE_Y = 16;
 // Block shapes of the step kernel: 0 = 256 threads, 4 outputs each along x;
-// 1 = 512 threads, 2 outputs each.
-constexpr int STEP_SHAPES = 2;
-// Kernel variant of a plan: the block shape, and + 2 for two feature channels
-// (float32 storage only).
-constexpr int kernel_shape(int shape, int nf) { return shape + 2 * (nf - 1); }
-constexpr int step_threads(int shape) { return shape == 0 ? 256 : 512; }
+// 1 = 512 threads, 2 outputs each; 2 = 256 threads with the spatial passes on
+// the matrix cores (float32 storage, one feature channel, r_t <= 2).
+constexpr int STEP_SHAPES = 3;
+constexpr int SHAPE_MFMA = 2;
+constexpr int MFMA_MAX_RT = 2;
+// Kernel variant of a plan: 0..2 the block shapes with one feature channel,
+// 3..4 shapes 0..1 with two (float32 storage only).
+constexpr int KERNEL_VARIANTS = 5;
+constexpr int kernel_shape(int shape, int nf) { return nf == 1 ? shape : 3 + shape; }
+constexpr int step_threads(int shape) { return shape == 1 ? 512 : 256; }
+// Whether a plan's block shape exists for a storage type, feature-channel
+// count and temporal radius (batched contexts: shapes 0..1 only).
+constexpr bool shape_supported(int shape, int dtype, int nf, int rt, bool batch) {
+    return shape >= 0 && shape < STEP_SHAPES &&
+           (shape != SHAPE_MFMA ||
+            (!batch && dtype == SFSEG_F32 && nf == 1 && rt <= MFMA_MAX_RT));
+}
 
 hipError_t launch_step(int dtype, int shape, int rs, int rt, const StepParams& p, int grid,
                        hipStream_t stream);

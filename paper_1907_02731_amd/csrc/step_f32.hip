@@ -1,15 +1,21 @@
 // Step-kernel instantiations for float storage: both block shapes, every
-// (r_s, r_t), single-clip and batched, and the two-feature-channel step.
+// (r_s, r_t), single-clip and batched, the matrix-core step and the
+// two-feature-channel step.
 #include "step_kernel.h"
+#include "step_mfma.h"
 
 namespace sfseg {
 
-// Kernel shapes 0, 1: one feature channel; 2, 3: two (step kernel only).
+// Kernel variants 0, 1: one feature channel; 2: matrix-core spatial passes
+// (one channel, r_t <= 2); 3, 4: two channels (step kernel only).
 static const detail::StepFns& fns_f32(int shape, int rs, int rt) {
     static const detail::StepTable<float> table;
+    static const detail::MfmaTable mfma;
     static const detail::StepTable2<float> table2;
     const int comb = rs * (SFSEG_MAX_RT + 1) + rt;
-    return shape < 2 ? table.fns[shape][comb] : table2.fns[shape - 2][comb];
+    if (shape < 2) return table.fns[shape][comb];
+    if (shape == SHAPE_MFMA) return mfma.fns[comb];
+    return table2.fns[shape - 3][comb];
 }
 
 hipError_t launch_step_f32(int shape, int rs, int rt, const StepParams& p, int grid,
