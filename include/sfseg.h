@@ -100,14 +100,19 @@ typedef struct {
 /* Work plan of the step kernel: block shape (0 = 256 threads with 4 outputs
  * each along x, 1 = 512 threads with 2, both filtering on the vector ALUs;
  * 2 = 256 threads with the y and x filter passes on the matrix cores, for
- * float32 storage, one feature channel and r_t <= 2 on single clips), number
- * of equal runs of frames each tile's time axis is cut into, and the
- * resulting grid.  Shapes 0 and 1 apply the same per-voxel arithmetic
- * whatever the plan; plans differ only in how the float64 partial sums of the
- * norms are grouped.  Shape 2 computes the same products in float32 with the
- * spatial filter sums taken on the matrix cores (each operand split into
- * float16 parts, float32 accumulation): its results agree with shapes 0/1 to
- * float32 rounding, not bit for bit. */
+ * float32 storage, one feature channel and r_t <= 2 on single clips; 3 = two
+ * power-iteration steps per launch and per pass over HBM (temporal
+ * blocking: the intermediate iterate and its halo recomputed in LDS on
+ * 32 x 8 tiles), float32 storage, one feature channel, r_s <= 5, r_t <= 2,
+ * single clips), number of equal runs of frames each tile's time axis is cut
+ * into, and the resulting grid.  Shapes 0 and 1 apply the same per-voxel
+ * arithmetic whatever the plan; plans differ only in how the float64 partial
+ * sums of the norms are grouped.  Shapes 2 and 3 compute the same products in
+ * float32 in another order (shape 2 with the spatial filter sums taken on
+ * the matrix cores, each operand split into float16 parts): their results
+ * agree with shapes 0/1 to float32 rounding, not bit for bit.  With shape 3
+ * a tolerance stop always completes a launch's pair of steps, so a run may
+ * take one step more than with the other shapes. */
 typedef struct {
     int32_t shape;
     int32_t chunks;
@@ -266,11 +271,12 @@ int sfseg_segment(sfseg_ctx *ctx, const float *x0, const sfseg_binarize *b, uint
 /* Current work plan of the step kernel.  Host only. */
 int sfseg_get_plan(const sfseg_ctx *ctx, sfseg_plan *out);
 
-/* Choose the work plan (see sfseg_plan): shape 0, 1 or 2, 1 <= chunks <=
+/* Choose the work plan (see sfseg_plan): shape 0 .. 3, 1 <= chunks <=
  * max(1, T / (4 r_t + 4)).  Blocks until the new work list is on the device;
  * SFSEG_ERR_INVALID_ARG for values out of range, SFSEG_ERR_UNSUPPORTED for
- * shape 2 where it does not exist (16-bit storage, two feature channels,
- * r_t > 2, batches).  Does not disturb the iterate. */
+ * shapes 2 and 3 where they do not exist (16-bit storage, two feature
+ * channels, radii beyond their limits, batches).  Does not disturb the
+ * iterate. */
 int sfseg_set_plan(sfseg_ctx *ctx, int32_t shape, int32_t chunks);
 
 /* Time `steps` steps of every candidate work plan (every block shape the

@@ -165,14 +165,19 @@ sfseg::Layout make_layout(const sfseg_config& c) {
 // Work items of the step kernel: every tile over `chunks` equal runs of
 // frames, chunk-major, then tile rows, then tile columns; padded with empty
 // items to a multiple of 8 blocks (one share per XCD).
-std::vector<int4> plan_items(const sfseg::Layout& L, int chunks) {
+std::vector<int4> plan_items(const sfseg::Layout& L, int chunks, int shape) {
+    // the fused two-step kernel works on smaller tiles (its LDS holds two
+    // steps' rings); they cover the same area as the 64 x 16 tiling
+    const bool fused = shape == sfseg::SHAPE_FUSED2;
+    const int tw = fused ? sfseg::FUSED_TILE_X : sfseg::TILE_X;
+    const int th = fused ? sfseg::FUSED_TILE_Y : sfseg::TILE_Y;
+    const int nx = L.tiles_x * (sfseg::TILE_X / tw), ny = L.tiles_y * (sfseg::TILE_Y / th);
     std::vector<int4> items;
     for (int ch = 0; ch < chunks; ++ch) {
         const int t0 = (int)((int64_t)L.T * ch / chunks), t1 = (int)((int64_t)L.T * (ch + 1) / chunks);
         if (t1 <= t0) continue;
-        for (int ty = 0; ty < L.tiles_y; ++ty)
-            for (int tx = 0; tx < L.tiles_x; ++tx)
-                items.push_back(make_int4(tx * sfseg::TILE_X, ty * sfseg::TILE_Y, t0, t1));
+        for (int ty = 0; ty < ny; ++ty)
+            for (int tx = 0; tx < nx; ++tx) items.push_back(make_int4(tx * tw, ty * th, t0, t1));
     }
     while (items.size() % 8) items.push_back(make_int4(0, 0, 0, 0));
     return items;
@@ -181,7 +186,7 @@ std::vector<int4> plan_items(const sfseg::Layout& L, int chunks) {
 // Install a work plan: block shape and number of frame runs per tile.  The
 // work items and the grid follow from it; a captured graph is dropped.
 int install_plan(sfseg_ctx* ctx, int shape, int chunks) {
-    const std::vector<int4> items = plan_items(ctx->L, chunks);
+    const std::vector<int4> items = plan_items(ctx->L, chunks, shape);
     if (items.size() > ctx->items_cap) {
         if (ctx->items) HIP_TRY(hipFree(ctx->items));
         ctx->items = nullptr;
@@ -199,7 +204,8 @@ int install_plan(sfseg_ctx* ctx, int shape, int chunks) {
     if (grid > ctx->step_part_slots) {
         if (ctx->step_part) HIP_TRY(hipFree(ctx->step_part));
         ctx->step_part = nullptr;
-        HIP_TRY(hipMalloc((void**)&ctx->step_part, sizeof(double) * 4 * grid));
+        // two sets (one per iterate buffer) of up to two pairs of sums per block
+        HIP_TRY(hipMalloc((void**)&ctx->step_part, sizeof(double) * 8 * grid));
         ctx->step_part_slots = grid;
     }
     HIP_TRY(hipMemcpyAsync(ctx->items, items.data(), sizeof(int4) * items.size(),
@@ -211,8 +217,9 @@ int install_plan(sfseg_ctx* ctx, int shape, int chunks) {
     for (int b = 0; b < 2; ++b) {
         StepParams& p = ctx->params[b];
         p.items = ctx->items;
-        p.part_in = ctx->step_part + 2 * (size_t)ctx->step_part_slots * b;
-        p.part_out = ctx->step_part + 2 * (size_t)ctx->step_part_slots * (1 - b);
+        p.part_in = ctx->step_part + 4 * (size_t)ctx->step_part_slots * b;
+        p.part_out = ctx->step_part + 4 * (size_t)ctx->step_part_slots * (1 - b);
+        p.half = 0;
     }
     if (ctx->graph) {
         (void)hipGraphExecDestroy(ctx->graph);
@@ -330,32 +337,47 @@ int run_init(hipStream_t stream, const sfseg_config& c, const sfseg::Layout& L, 
     return SFSEG_OK;
 }
 
-int launch_steps(sfseg_ctx* ctx, int first_buf, int count) {
-    for (int i = 0; i < count; ++i) {
-        const int b = (first_buf + i) & 1;
+int launch_steps(sfseg_ctx* ctx, int first_buf, int count, int* last_buf) {
+    // one launch per step, or per two steps with the fused kernel (an odd
+    // last step in its one-step mode); launches alternate the two buffers
+    const int per = sfseg::steps_per_launch(ctx->shape);
+    int b = first_buf & 1;
+    for (int done = 0; done < count;) {
+        sfseg::StepParams p = ctx->params[b];
+        p.half = count - done < per ? 1 : 0;
         HIP_TRY(sfseg::launch_step(ctx->cfg.storage, sfseg::kernel_shape(ctx->shape, ctx->nf),
-                                   ctx->cfg.r_s, ctx->cfg.r_t,
-                                   ctx->params[b], ctx->step_grid, ctx->stream));
+                                   ctx->cfg.r_s, ctx->cfg.r_t, p, ctx->step_grid, ctx->stream));
+        done += p.half ? 1 : per;
+        b ^= 1;
     }
+    if (last_buf) *last_buf = b;
     return SFSEG_OK;
 }
 
 int launch_finish(sfseg_ctx* ctx, int slot) {
     HIP_TRY(sfseg::launch_step_finish(ctx->st, slot & 1,
-                                      ctx->step_part + 2 * (size_t)ctx->step_part_slots * (slot & 1),
+                                      ctx->step_part + 4 * (size_t)ctx->step_part_slots * (slot & 1),
                                       ctx->step_grid, ctx->stream));
     return SFSEG_OK;
 }
 
-// kChunk steps from buf[0] (kChunk is even, so they end in buf[0]) and the
-// fold of the last one.
-static_assert(kChunk % 2 == 0, "a captured chunk must end in buf[0]");
+// Buffer that holds the iterate after k steps from buf[0]: launches
+// alternate the buffers, and the fused kernel takes two steps per launch
+// (only the last launch of a run can take one).
+int buffer_after(const sfseg_ctx* ctx, int k) {
+    return sfseg::steps_per_launch(ctx->shape) == 2 ? ((k + 1) / 2) & 1 : k & 1;
+}
+
+// kChunk steps from buf[0] (kChunk / 2 is even as well, so with one or two
+// steps per launch they end in buf[0]) and the fold of the last one.
+static_assert(kChunk % 4 == 0, "a captured chunk must end in buf[0]");
 int ensure_graph(sfseg_ctx* ctx) {
     if (ctx->graph) return SFSEG_OK;
     hipGraph_t g = nullptr;
     HIP_TRY(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
-    int rc = launch_steps(ctx, 0, kChunk);
-    if (rc == SFSEG_OK) rc = launch_finish(ctx, kChunk & 1);
+    int last = 0;
+    int rc = launch_steps(ctx, 0, kChunk, &last);
+    if (rc == SFSEG_OK) rc = launch_finish(ctx, last);
     hipError_t e = hipStreamEndCapture(ctx->stream, &g);
     if (rc != SFSEG_OK) {
         if (g) (void)hipGraphDestroy(g);
@@ -440,17 +462,18 @@ int sfseg_power_iterate(sfseg_ctx* ctx, const float* x0, int32_t max_iters, doub
     // Keep up to two chunks in flight: while chunk i runs, chunk i+1 is queued
     // and the host inspects the state copied out after chunk i-1.
     int launched = 0, enq = 0, chk = 0;
+    int cur = 0;  // buffer holding the iterate after `launched` steps
     const bool use_graph = ctx->stream != nullptr && ensure_graph(ctx) == SFSEG_OK;
     while (true) {
         while (enq - chk < 2 && launched < max_iters) {
             const int remaining = max_iters - launched;
-            if (use_graph && remaining >= kChunk && (launched & 1) == 0) {
+            if (use_graph && remaining >= kChunk && cur == 0) {
                 HIP_TRY(hipGraphLaunch(ctx->graph, ctx->stream));
                 launched += kChunk;
             } else {
                 const int cnt = remaining < kChunk ? remaining : kChunk;
-                int rc = launch_steps(ctx, launched & 1, cnt);
-                if (rc == SFSEG_OK) rc = launch_finish(ctx, (launched + cnt) & 1);
+                int rc = launch_steps(ctx, cur, cnt, &cur);
+                if (rc == SFSEG_OK) rc = launch_finish(ctx, cur);
                 if (rc != SFSEG_OK) return rc;
                 launched += cnt;
             }
@@ -492,7 +515,7 @@ int sfseg_power_iterate(sfseg_ctx* ctx, const float* x0, int32_t max_iters, doub
                                   : "non-finite value (start vector or iterate %d)",
                     s.k);
     }
-    ctx->cur = s.k & 1;
+    ctx->cur = buffer_after(ctx, s.k);
     ctx->have_iterate = true;
     return SFSEG_OK;
 }
@@ -549,6 +572,7 @@ int apply_async(sfseg_ctx* ctx, const float* x, float* y) {
     p.y = ctx->apply_out;
     p.st_in = ctx->st_apply;
     p.st_out = ctx->st_apply + 1;
+    p.half = 1;  // one application (the fused kernel's one-step mode)
     HIP_TRY(sfseg::launch_step(ctx->cfg.storage, sfseg::kernel_shape(ctx->shape, ctx->nf),
                                ctx->cfg.r_s, ctx->cfg.r_t, p,
                                ctx->step_grid, ctx->stream));
@@ -576,10 +600,12 @@ int sfseg_set_plan(sfseg_ctx* ctx, int32_t shape, int32_t chunks) {
     if (ctx->batch) return batch_set_plan(ctx, shape, chunks);
     if (shape < 0 || shape >= sfseg::STEP_SHAPES)
         return fail(SFSEG_ERR_INVALID_ARG, "shape must be 0..%d", sfseg::STEP_SHAPES - 1);
-    if (!sfseg::shape_supported(shape, ctx->cfg.storage, ctx->nf, ctx->cfg.r_t, false))
+    if (!sfseg::shape_supported(shape, ctx->cfg.storage, ctx->nf, ctx->cfg.r_s, ctx->cfg.r_t,
+                                false))
         return fail(SFSEG_ERR_UNSUPPORTED,
-                    "shape %d needs float32 storage, one feature channel and r_t <= %d", shape,
-                    sfseg::MFMA_MAX_RT);
+                    "shape %d needs float32 storage, one feature channel and radii within "
+                    "its limits (r_t <= %d; fused: r_s <= %d, r_t <= %d)",
+                    shape, sfseg::MFMA_MAX_RT, sfseg::FUSED_MAX_RS, sfseg::FUSED_MAX_RT);
     if (chunks < 1 || chunks > max_chunks(ctx->cfg))
         return fail(SFSEG_ERR_INVALID_ARG, "chunks must be 1..%d for this clip", max_chunks(ctx->cfg));
     HIP_TRY(hipSetDevice(ctx->device));

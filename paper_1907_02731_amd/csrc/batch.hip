@@ -208,7 +208,7 @@ int batch_get_plan(const sfseg_ctx* ctx, sfseg_plan* out) {
 int batch_set_plan(sfseg_ctx* ctx, int32_t shape, int32_t chunks) {
     if (shape < 0 || shape >= sfseg::STEP_SHAPES)
         return fail(SFSEG_ERR_INVALID_ARG, "shape must be 0..%d", sfseg::STEP_SHAPES - 1);
-    if (!sfseg::shape_supported(shape, ctx->cfg.storage, ctx->nf, ctx->cfg.r_t, true))
+    if (!sfseg::shape_supported(shape, ctx->cfg.storage, ctx->nf, ctx->cfg.r_s, ctx->cfg.r_t, true))
         return fail(SFSEG_ERR_UNSUPPORTED, "shape %d is not available for batches", shape);
     int most = 1;
     for (auto& c : ctx->batch->clips) most = std::max(most, max_chunks(c.cfg));
@@ -451,7 +451,7 @@ int sfseg_autotune(sfseg_ctx* ctx, int32_t steps, sfseg_plan* best) {
     int best_shape = ctx->shape, best_chunks = ctx->chunks;
     const int chunk_opts[] = {1, 2, 3, 4};
     for (int shape = 0; shape < sfseg::STEP_SHAPES; ++shape) {
-        if (!sfseg::shape_supported(shape, ctx->cfg.storage, ctx->nf, ctx->cfg.r_t,
+        if (!sfseg::shape_supported(shape, ctx->cfg.storage, ctx->nf, ctx->cfg.r_s, ctx->cfg.r_t,
                                     ctx->batch != nullptr))
             continue;
         for (int ch : chunk_opts) {

@@ -387,7 +387,7 @@ int sfseg_segment(sfseg_ctx* ctx, const float* x0, const sfseg_binarize* b, uint
     HIP_TRY(hipEventRecord(ctx->ev[1], ctx->stream));
     const int grid = bin_grid(ctx);
     for (int k = 1; k <= b->iters; ++k) {
-        rc = launch_steps(ctx, (k - 1) & 1, 1);
+        rc = launch_steps(ctx, (k - 1) & 1, 1, nullptr);
         if (rc != SFSEG_OK) return rc;
         if (b->project_from <= k && k < b->iters) {
             rc = launch_finish(ctx, k & 1);  // the projection needs the step's norm

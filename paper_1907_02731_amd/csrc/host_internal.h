@@ -45,8 +45,11 @@ struct sfseg_ctx;
 
 namespace sfseg_host {
 int batch_get_plan(const sfseg_ctx* ctx, sfseg_plan* out);
-// Enqueue `count` single steps, the first from buf[first_buf & 1].
-int launch_steps(sfseg_ctx* ctx, int first_buf, int count);
+// Enqueue `count` steps, the first from buf[first_buf & 1]; *last_buf (may
+// be NULL) receives the buffer that holds the result.
+int launch_steps(sfseg_ctx* ctx, int first_buf, int count, int* last_buf);
+// Buffer that holds the iterate after k steps of a run from buf[0].
+int buffer_after(const sfseg_ctx* ctx, int k);
 // Enqueue the one-block fold that completes the state of buf[slot] (the last
 // step's output) and makes slot 0 current.
 int launch_finish(sfseg_ctx* ctx, int slot);

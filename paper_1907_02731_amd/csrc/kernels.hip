@@ -253,14 +253,15 @@ dim3 ew_dims(const Layout& L, int blocks) {
 }  // namespace
 
 // `shape` is a kernel variant (kernel_shape): 0..1 for every storage type,
-// 2 (matrix-core spatial passes, r_t <= 2) and 3..4 (two feature channels)
-// for float32 only.
+// 2 (matrix-core spatial passes, r_t <= 2), 3 (two fused steps, r_s <= 5,
+// r_t <= 2) and 4..5 (two feature channels) for float32 only.
 static bool variant_ok(int dtype, int shape, int rs, int rt) {
     if (shape < 0 || shape >= KERNEL_VARIANTS || rs < 0 || rs > SFSEG_MAX_RS || rt < 0 ||
         rt > SFSEG_MAX_RT)
         return false;
     if (shape >= 2 && dtype != SFSEG_F32) return false;
     if (shape == SHAPE_MFMA && rt > MFMA_MAX_RT) return false;
+    if (shape == SHAPE_FUSED2 && (rs > FUSED_MAX_RS || rt > FUSED_MAX_RT)) return false;
     return true;
 }
 

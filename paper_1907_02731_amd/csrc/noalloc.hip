@@ -125,6 +125,7 @@ int sfseg_apply_noalloc(sfseg_ctx* ctx, const float* x, float* y) {
     p.st_out = st + 1;
     p.part_in = partials;
     p.part_out = partials;
+    p.half = 1;  // one application (the fused kernel's one-step mode)
     HIP_TRY(sfseg::launch_step(ctx->cfg.storage, sfseg::kernel_shape(ctx->shape, ctx->nf),
                                ctx->cfg.r_s, ctx->cfg.r_t, p, ctx->step_grid, ctx->stream));
     HIP_TRY(sfseg::launch_from_storage(ctx->cfg.storage, out, y, ctx->L, ctx->ew_grid,

@@ -36,8 +36,8 @@ struct DevState {
     int32_t done;       // 1: later step launches return at once
     int32_t status;     // SFSEG_OK or the error that stopped the iteration
     int32_t converged;  // delta < tol reached
-    int32_t pending;    // 1: the partial sums of the step that wrote this slot's buffer
-                        // are not folded in yet (single clips)
+    int32_t pending;    // 1 (2): the partial sums of the step (the two fused steps) that
+                        // wrote this slot's buffer are not folded in yet (single clips)
 };
 
 // Zero-padded storage layout of every internal volume: frames of Hp x Wp
@@ -70,6 +70,7 @@ struct StepParams {
     float gs[SFSEG_MAX_RS + 1];  // spatial taps g_s[d], d = 0..r_s
     float gt[SFSEG_MAX_RT + 1];  // temporal taps g_t[d], d = 0..r_t
     float alpha;
+    int32_t half;  // fused two-step kernel: stop after the first step
 };
 
 // One clip of a batch, as the batched step kernel sees it.
@@ -102,21 +103,32 @@ constexpr int TILE_X = 64;
 constexpr int TILE_Y = 16;
 // Block shapes of the step kernel: 0 = 256 threads, 4 outputs each along x;
 // 1 = 512 threads, 2 outputs each; 2 = 256 threads with the spatial passes on
-// the matrix cores (float32 storage, one feature channel, r_t <= 2).
-constexpr int STEP_SHAPES = 3;
+// the matrix cores (float32 storage, one feature channel, r_t <= 2); 3 = two
+// steps fused per launch on 32 x 8 tiles (float32 storage, one feature
+// channel, r_s <= 5, r_t <= 2).
+constexpr int STEP_SHAPES = 4;
 constexpr int SHAPE_MFMA = 2;
+constexpr int SHAPE_FUSED2 = 3;
 constexpr int MFMA_MAX_RT = 2;
-// Kernel variant of a plan: 0..2 the block shapes with one feature channel,
-// 3..4 shapes 0..1 with two (float32 storage only).
-constexpr int KERNEL_VARIANTS = 5;
-constexpr int kernel_shape(int shape, int nf) { return nf == 1 ? shape : 3 + shape; }
+constexpr int FUSED_MAX_RS = 5;
+constexpr int FUSED_MAX_RT = 2;
+constexpr int FUSED_TILE_X = 32;
+constexpr int FUSED_TILE_Y = 8;
+// Kernel variant of a plan: 0..3 the block shapes with one feature channel,
+// 4..5 shapes 0..1 with two (float32 storage only).
+constexpr int KERNEL_VARIANTS = 6;
+constexpr int kernel_shape(int shape, int nf) { return nf == 1 ? shape : STEP_SHAPES + shape; }
 constexpr int step_threads(int shape) { return shape == 1 ? 512 : 256; }
+// Steps one launch of a plan's kernel takes.
+constexpr int steps_per_launch(int shape) { return shape == SHAPE_FUSED2 ? 2 : 1; }
 // Whether a plan's block shape exists for a storage type, feature-channel
-// count and temporal radius (batched contexts: shapes 0..1 only).
-constexpr bool shape_supported(int shape, int dtype, int nf, int rt, bool batch) {
+// count and radii (batched contexts: shapes 0..1 only).
+constexpr bool shape_supported(int shape, int dtype, int nf, int rs, int rt, bool batch) {
     return shape >= 0 && shape < STEP_SHAPES &&
            (shape != SHAPE_MFMA ||
-            (!batch && dtype == SFSEG_F32 && nf == 1 && rt <= MFMA_MAX_RT));
+            (!batch && dtype == SFSEG_F32 && nf == 1 && rt <= MFMA_MAX_RT)) &&
+           (shape != SHAPE_FUSED2 || (!batch && dtype == SFSEG_F32 && nf == 1 &&
+                                      rs <= FUSED_MAX_RS && rt <= FUSED_MAX_RT));
 }
 
 hipError_t launch_step(int dtype, int shape, int rs, int rt, const StepParams& p, int grid,

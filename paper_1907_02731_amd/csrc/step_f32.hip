@@ -1,21 +1,25 @@
 // Step-kernel instantiations for float storage: both block shapes, every
 // (r_s, r_t), single-clip and batched, the matrix-core step and the
 // two-feature-channel step.
+#include "step_fused.h"
 #include "step_kernel.h"
 #include "step_mfma.h"
 
 namespace sfseg {
 
 // Kernel variants 0, 1: one feature channel; 2: matrix-core spatial passes
-// (one channel, r_t <= 2); 3, 4: two channels (step kernel only).
+// (one channel, r_t <= 2); 3: two fused steps (one channel, r_s <= 5,
+// r_t <= 2); 4, 5: two channels (step kernel only).
 static const detail::StepFns& fns_f32(int shape, int rs, int rt) {
     static const detail::StepTable<float> table;
     static const detail::MfmaTable mfma;
+    static const detail::FusedTable fused;
     static const detail::StepTable2<float> table2;
     const int comb = rs * (SFSEG_MAX_RT + 1) + rt;
     if (shape < 2) return table.fns[shape][comb];
     if (shape == SHAPE_MFMA) return mfma.fns[comb];
-    return table2.fns[shape - 3][comb];
+    if (shape == SHAPE_FUSED2) return fused.fns[comb];
+    return table2.fns[shape - STEP_SHAPES][comb];
 }
 
 hipError_t launch_step_f32(int shape, int rs, int rt, const StepParams& p, int grid,

@@ -308,16 +308,34 @@ __device__ void fold_partials(const double* part, int nblocks, double (*red)[4],
 }
 
 // The state of a step launch's input: the slot as written, with the partial
-// sums of the step that wrote the input folded in if they are pending.
+// sums of the launch that wrote the input folded in if they are pending.  A
+// launch of two fused steps (pending = 2) leaves a second set of sums after
+// the first (part + 2 nblocks); both of its steps used the multiplier c of
+// its own input, so the second advance starts from that c again.  The pair
+// is always taken whole: if the first step already met the tolerance, the
+// state still ends at the second, which is the iterate in the buffer.
 template <int NT>
 __device__ DevState state_of_input(const DevState* slot, const double* part, int nblocks,
                                    double (*red)[4]) {
     DevState s = *slot;
     if (s.pending) {
+        const int np = s.pending;
+        const float c_used = s.c;
         double syy, syx;
         fold_partials<NT>(part, nblocks, red, syy, syx);
         s.pending = 0;
         advance_values(s, syy, syx);
+        if (np == 2 && s.status == SFSEG_OK) {
+            const int conv = s.converged;
+            fold_partials<NT>(part + 2 * nblocks, nblocks, red, syy, syx);
+            s.c = c_used;
+            s.done = 0;
+            advance_values(s, syy, syx);
+            if (conv) {
+                s.converged = 1;
+                s.done = 1;
+            }
+        }
     }
     return s;
 }

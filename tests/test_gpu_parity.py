@@ -320,7 +320,7 @@ def test_every_plan_gives_the_same_trajectory(long_clip, shape, chunks):
 def test_plan_rejects_bad_values(tiny):
     S, _ = tiny
     with _solver(S) as sol:
-        for shape, chunks in ((3, 1), (-1, 1), (0, 0), (0, 10_000)):
+        for shape, chunks in ((4, 1), (-1, 1), (0, 0), (0, 10_000)):
             with pytest.raises(_lib.SfsegError) as e:
                 sol.set_plan(shape, chunks)
             assert e.value.status == _lib.SFSEG_ERR_INVALID_ARG
