@@ -174,7 +174,8 @@ def parse():
     ap.add_argument("--iters", type=int, default=0,
                     help="run exactly this many steps per solve (tol = 0); for profiling")
     ap.add_argument("--shape", type=int, default=-1, help="step-kernel block shape (0/1)")
-    ap.add_argument("--chunks", type=int, default=0, help="frame runs per tile")
+    ap.add_argument("--chunks", type=int, default=-1,
+                    help="frame runs per tile (0: the balanced work list)")
     ap.add_argument("--precision-report", action="store_true",
                     help="for 16-bit storage: error of the final iterate against the float32 "
                          "result after the same number of steps, and the FP64 oracle's residual "
@@ -287,10 +288,10 @@ def batch_measure(args, storage: str = "f32", reps: int = None, warmup: int = No
     max_iters, tol = (args.iters, 0.0) if args.iters > 0 else (args.max_iters, args.tol)
     bs = BatchSolver(clips, **kw)
     plan_info = bs.autotune(steps=16, cache=args.plan_cache or None) if args.autotune else None
-    if args.shape >= 0 or args.chunks > 0:
+    if args.shape >= 0 or args.chunks >= 0:
         pl = bs.plan()
         bs.set_plan(args.shape if args.shape >= 0 else pl["shape"],
-                    args.chunks if args.chunks > 0 else pl["chunks"])
+                    args.chunks if args.chunks >= 0 else pl["chunks"])
 
     def batched():
         r = bs.iterate(max_iters=max_iters, tol=tol)
@@ -598,10 +599,10 @@ def main():
               storage=args.storage)
     sol = Solver(St, Ft, **kw)
     plan_info = sol.autotune(steps=32, cache=args.plan_cache or None) if args.autotune else None
-    if args.shape >= 0 or args.chunks > 0:
+    if args.shape >= 0 or args.chunks >= 0:
         pl = sol.plan()
         sol.set_plan(args.shape if args.shape >= 0 else pl["shape"],
-                     args.chunks if args.chunks > 0 else pl["chunks"])
+                     args.chunks if args.chunks >= 0 else pl["chunks"])
 
     max_iters, tol = (args.iters, 0.0) if args.iters > 0 else (args.max_iters, args.tol)
 

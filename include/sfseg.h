@@ -272,7 +272,12 @@ int sfseg_segment(sfseg_ctx *ctx, const float *x0, const sfseg_binarize *b, uint
 int sfseg_get_plan(const sfseg_ctx *ctx, sfseg_plan *out);
 
 /* Choose the work plan (see sfseg_plan): shape 0 .. 3, 1 <= chunks <=
- * max(1, T / (4 r_t + 4)).  Blocks until the new work list is on the device;
+ * max(1, T / (4 r_t + 4)), or chunks = 0 for shapes 0 and 1 on single clips:
+ * the balanced work list, where each XCD gets a contiguous band of tiles and
+ * exactly two work items per resident block slot, some tiles cut into one run
+ * of frames more than others, longest items first (SFSEG_ERR_INVALID_ARG if
+ * the clip has fewer than 8 tiles or too few frames for it).  Blocks until the
+ * new work list is on the device;
  * SFSEG_ERR_INVALID_ARG for values out of range, SFSEG_ERR_UNSUPPORTED for
  * shapes 2 and 3 where they do not exist (16-bit storage, two feature
  * channels, radii beyond their limits, batches).  Does not disturb the
@@ -280,8 +285,8 @@ int sfseg_get_plan(const sfseg_ctx *ctx, sfseg_plan *out);
 int sfseg_set_plan(sfseg_ctx *ctx, int32_t shape, int32_t chunks);
 
 /* Time `steps` steps of every candidate work plan (every block shape the
- * context supports, 1..4 frame runs per tile where the clip allows) from the
- * default start vector,
+ * context supports, 1..4 frame runs per tile where the clip allows, and the
+ * balanced work list) from the default start vector,
  * keep the fastest, and report it in *best (may be NULL).  Works on single
  * and batch contexts.  Leaves no iterate (call the iterate entry point
  * again).  Blocks for the whole search. */

@@ -165,6 +165,43 @@ sfseg::Layout make_layout(const sfseg_config& c) {
 // Work items of the step kernel: every tile over `chunks` equal runs of
 // frames, chunk-major, then tile rows, then tile columns; padded with empty
 // items to a multiple of 8 blocks (one share per XCD).
+// Balanced work list (chunks = 0, vector shapes): each of the 8 XCDs gets a
+// contiguous band of tiles and exactly two items per resident block slot of
+// its CUs; a band's tiles are cut into runs of frames -- some tiles one run
+// more than others -- to make up that count, and the band's items go longest
+// first, run by run, so that the blocks the dispatcher hands out last are
+// the short ones.  Two items per slot fill the slots in two even waves
+// instead of the 1.6 waves of three equal runs per tile, for a few more
+// warm-up frames.  Returns an empty list when the clip has too few tiles or
+// frames for it (every band needs at least one tile, every run 4 r_t + 4
+// frames).
+std::vector<int4> balanced_items(const sfseg::Layout& L, int slots, int most_runs) {
+    std::vector<int4> items;
+    const int tiles = L.tiles_x * L.tiles_y;
+    const int per_band = 2 * (slots / 8);
+    if (tiles < 8 || per_band < 1) return items;
+    for (int band = 0; band < 8; ++band) {
+        const int a = tiles * band / 8, b = tiles * (band + 1) / 8;
+        const int n = b - a;
+        const int lo = per_band / n, extra = per_band - lo * n;  // `extra` tiles get lo + 1
+        if (lo < 1 || lo + (extra ? 1 : 0) > most_runs) return std::vector<int4>();
+        // longest items first: the tiles with lo runs (the last n - extra of
+        // the band), then those with lo + 1
+        for (int pass = 0; pass < 2; ++pass) {
+            const int runs = pass == 0 ? lo : lo + 1;
+            const int t_first = pass == 0 ? a + extra : a, t_last = pass == 0 ? b : a + extra;
+            for (int r = 0; r < runs; ++r) {
+                const int t0 = (int)((int64_t)L.T * r / runs), t1 = (int)((int64_t)L.T * (r + 1) / runs);
+                for (int t = t_first; t < t_last; ++t) {
+                    const int tx = t % L.tiles_x, ty = t / L.tiles_x;
+                    items.push_back(make_int4(tx * sfseg::TILE_X, ty * sfseg::TILE_Y, t0, t1));
+                }
+            }
+        }
+    }
+    return items;
+}
+
 std::vector<int4> plan_items(const sfseg::Layout& L, int chunks, int shape) {
     // the fused two-step kernel works on smaller tiles (its LDS holds two
     // steps' rings); they cover the same area as the 64 x 16 tiling
@@ -186,7 +223,18 @@ std::vector<int4> plan_items(const sfseg::Layout& L, int chunks, int shape) {
 // Install a work plan: block shape and number of frame runs per tile.  The
 // work items and the grid follow from it; a captured graph is dropped.
 int install_plan(sfseg_ctx* ctx, int shape, int chunks) {
-    const std::vector<int4> items = plan_items(ctx->L, chunks, shape);
+    std::vector<int4> items;
+    if (chunks == 0) {
+        int occ = 1;
+        HIP_TRY(sfseg::step_max_blocks_per_cu(ctx->cfg.storage, sfseg::kernel_shape(shape, ctx->nf),
+                                              ctx->cfg.r_s, ctx->cfg.r_t, &occ));
+        items = balanced_items(ctx->L, ctx->cus * (occ < 1 ? 1 : occ), max_chunks(ctx->cfg));
+        if (items.empty())
+            return fail(SFSEG_ERR_INVALID_ARG,
+                        "the clip has too few tiles or frames for the balanced plan (chunks = 0)");
+    } else {
+        items = plan_items(ctx->L, chunks, shape);
+    }
     if (items.size() > ctx->items_cap) {
         if (ctx->items) HIP_TRY(hipFree(ctx->items));
         ctx->items = nullptr;
@@ -606,7 +654,9 @@ int sfseg_set_plan(sfseg_ctx* ctx, int32_t shape, int32_t chunks) {
                     "shape %d needs float32 storage, one feature channel and radii within "
                     "its limits (r_t <= %d; fused: r_s <= %d, r_t <= %d)",
                     shape, sfseg::MFMA_MAX_RT, sfseg::FUSED_MAX_RS, sfseg::FUSED_MAX_RT);
-    if (chunks < 1 || chunks > max_chunks(ctx->cfg))
+    if (chunks == 0 && shape > 1)
+        return fail(SFSEG_ERR_UNSUPPORTED, "the balanced plan (chunks = 0) is for shapes 0 and 1");
+    if (chunks < 0 || chunks > max_chunks(ctx->cfg))
         return fail(SFSEG_ERR_INVALID_ARG, "chunks must be 1..%d for this clip", max_chunks(ctx->cfg));
     HIP_TRY(hipSetDevice(ctx->device));
     return install_plan(ctx, shape, chunks);

@@ -449,14 +449,16 @@ int sfseg_autotune(sfseg_ctx* ctx, int32_t steps, sfseg_plan* best) {
     }
     double best_ms = 1e300;
     int best_shape = ctx->shape, best_chunks = ctx->chunks;
-    const int chunk_opts[] = {1, 2, 3, 4};
+    // frame runs per tile; 0 = the balanced work list (single clips, shapes 0, 1)
+    const int chunk_opts[] = {1, 2, 3, 4, 0};
     for (int shape = 0; shape < sfseg::STEP_SHAPES; ++shape) {
         if (!sfseg::shape_supported(shape, ctx->cfg.storage, ctx->nf, ctx->cfg.r_s, ctx->cfg.r_t,
                                     ctx->batch != nullptr))
             continue;
         for (int ch : chunk_opts) {
-            if (ch > most) continue;
+            if (ch > most || (ch == 0 && (ctx->batch || shape > 1))) continue;
             int rc = sfseg_set_plan(ctx, shape, ch);
+            if (rc != SFSEG_OK && ch == 0) continue;  // the clip is too small for it
             if (rc != SFSEG_OK) return rc;
             double ms = 1e300;
             for (int rep = 0; rep < 2; ++rep) {  // first run warms caches and captures the graph

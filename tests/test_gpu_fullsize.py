@@ -143,3 +143,38 @@ def test_batch_members_50_steps_on_the_tuned_plan():
               f"||x_gpu - x_oracle|| = {err:.3e}, lambda rel {lam_rel:.3e}", flush=True)
         assert err <= 1e-5
         assert lam_rel <= 1e-6
+
+
+def test_balanced_work_list_on_the_full_clip(full_oracle):
+    """The balanced work list (chunks = 0: two items per resident block slot,
+    some tiles cut into one more run of frames than others): one
+    application equals that of the tuned plan bit for bit (the per-voxel
+    arithmetic does not depend on the plan), and 100 steps match the FP64
+    oracle."""
+    S, ref = full_oracle
+    x = np.random.Generator(np.random.PCG64(77)).random(S.shape).astype(np.float32)
+    ys = []
+    for plan in ((0, 3), (0, 0)):
+        with Solver(_t(S), **KW) as sol:
+            sol.set_plan(*plan)
+            pl = sol.plan()
+            ys.append(sol.apply(_t(x)).cpu().numpy())
+            if plan == (0, 0):
+                assert pl["chunks"] == 0 and pl["blocks"] % 8 == 0
+                res = sol.iterate(max_iters=K_FULL, tol=0.0)
+                xg = sol.eigvec().cpu().numpy().astype(np.float64).ravel()
+    assert np.array_equal(ys[0], ys[1])
+    err = float(np.linalg.norm(xg - ref["x"]))
+    print(f"\nbalanced plan {pl}: ||x_gpu - x_oracle|| = {err:.3e} after {K_FULL} steps",
+          flush=True)
+    assert res.iters == K_FULL and err <= 1e-5
+    assert abs(res.lam - ref["lam"]) <= 1e-6 * ref["lam"]
+
+
+def test_balanced_work_list_needs_a_large_clip():
+    from paper_1907_02731_amd import _lib
+    S = full_clip(2, T=8, H=64, W=96)
+    with Solver(_t(S), **KW) as sol:
+        with pytest.raises(_lib.SfsegError) as e:
+            sol.set_plan(0, 0)
+        assert e.value.status == _lib.SFSEG_ERR_INVALID_ARG
