@@ -119,10 +119,14 @@ def test_training_gains_over_cold_start():
     """A short training run on small clips.  The loss falls; on held-out clips
     the network's estimate is much closer to the principal eigenvector than
     the input map S is; started from it, the plain method reaches the same
-    eigenvector (same Rayleigh quotient) in no more steps on average.  (How
-    many steps it saves depends on how much of the start vector's error lies
-    along the slowest subdominant eigenvectors; the full-resolution comparison
-    is the benchmark's warm-start workload.)"""
+    eigenvector in fewer steps on average (strictly).  Same eigenvector: the
+    Rayleigh quotients agree to 1e-6, and the two vectors lie within the sum
+    of their distances to v_1 as the convergence rate bounds them: after a
+    stop at change delta the error left is about delta r / (1 - r), r the
+    measured per-step contraction (lambda_2 / lambda_1, taken from the change
+    over the last 20 steps of the cold run), with a factor 3 for the
+    pre-asymptotic steps.  Wall time including inference is printed; the
+    full-resolution comparison is the benchmark's warm-start workload."""
     shape = (16, 64, 96)
     graph = dict(r_t=2, r_s=5, sigma_t=1.0, sigma_s=2.0, alpha=1.0, p=0.2)
     clips = [make_clip(*shape, seed=70000 + i, n_blobs=3, noise_sigma=0.15, motion="affine",
@@ -141,19 +145,32 @@ def test_training_gains_over_cold_start():
         first, last = np.mean(losses[:24]), np.mean(losses[-24:])
         print(f"loss: first 24 steps {first:.4f}, last 24 steps {last:.4f}", flush=True)
         assert last < 0.2 * first
-        cold_it, warm_it, e_s, e_net = [], [], [], []
+        cold_it, warm_it, e_s, e_net, t_cold, t_warm = [], [], [], [], [], []
         for S, t in zip(inputs[48:], tg[48:]):
             e_s.append(cos_err(S, t))
             e_net.append(cos_err(net.forward(S), t))
-            rc, xc, _ = solve_cold(S, tol=1e-5, graph=graph)
-            rw, xw, _, _ = solve_warm(S, net, tol=1e-5, graph=graph)
+            rc, xc, tc = solve_cold(S, tol=1e-5, graph=graph)
+            rw, xw, tw, _ = solve_warm(S, net, tol=1e-5, graph=graph)
             assert rc.converged and rw.converged
             assert abs(rw.lam - rc.lam) <= 1e-6 * rc.lam
-            assert float(torch.linalg.norm(xw - xc)) <= 2e-2
+            # per-step contraction from the cold run's change over its last 20 steps
+            r20 = solve_cold(S, tol=0.0, graph=graph, max_iters=rc.iters - 20)[0]
+            rate = (rc.delta / r20.delta) ** (1.0 / 20)
+            assert 0.0 < rate < 1.0
+            bound = 3.0 * (rc.delta + rw.delta) * rate / (1.0 - rate)
+            d = float(np.linalg.norm(xw.cpu().numpy().astype(np.float64) -
+                                     xc.cpu().numpy().astype(np.float64)))
+            print(f"  contraction {rate:.4f}: ||x_warm - x_cold|| = {d:.2e} <= {bound:.2e}",
+                  flush=True)
+            assert d <= bound
             cold_it.append(rc.iters)
             warm_it.append(rw.iters)
+            t_cold.append(tc)
+            t_warm.append(tw)
     print(f"held-out 1 - cos to the eigenvector: S {np.mean(e_s):.4f}, network {np.mean(e_net):.4f}",
           flush=True)
     print(f"held-out steps to 1e-5: cold {cold_it} warm {warm_it}", flush=True)
+    print(f"held-out time to 1e-5 (warm includes inference): cold {1e3 * np.mean(t_cold):.2f} ms, "
+          f"warm {1e3 * np.mean(t_warm):.2f} ms", flush=True)
     assert np.mean(e_net) <= 0.25 * np.mean(e_s)
-    assert np.mean(warm_it) <= np.mean(cold_it)
+    assert np.mean(warm_it) < np.mean(cold_it)
