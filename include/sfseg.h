@@ -195,6 +195,28 @@ int sfseg_apply(sfseg_ctx *ctx, const float *x, float *y);
 int sfseg_spectral_grad(sfseg_ctx *ctx, const float *xhat, const float *target, int32_t k,
                         float *grad, double *loss);
 
+/* Frame-wise Rayleigh-Ritz refinement of the current iterate, a start vector
+ * for the warm-started form (an addition, not in the paper).  Eq. (3)
+ * defines the principal eigenvector as the maximiser of the Rayleigh
+ * quotient; this call maximises it over the span of the iterate's frames:
+ * with q_t = x_k on frame t (zero elsewhere), B[i][j] = q_i^T M q_j (a band
+ * matrix: M couples frames at most r_t apart) and G = diag(|q_t|^2), it
+ * writes x_out = sum_t a_t q_t, a the top eigenvector of B a = mu G a, signed
+ * for a positive overlap with x_k and scaled to unit norm (frames where x_k
+ * is zero get a_t = 0).  x_out is a device float32 T*H*W volume owned by the
+ * caller; pass it as x0 to sfseg_power_iterate, which then runs Eq. (4) and
+ * Eq. (8) unchanged to its tolerance.  *ritz_value (host, may be NULL)
+ * receives mu, the Rayleigh quotient of x_out (<= lambda_1).
+ * B takes 2 r_t + 1 products of M through the context's step kernel and
+ * plan (frames of one residue modulo 2 r_t + 1 at a time) on the iterate as
+ * stored; frame sums are float64, and the band problem is solved on the host
+ * in float64.  Allocates two staging volumes and the frame sums on the first
+ * call (kept until sfseg_destroy); blocks until x_out is written.  Errors:
+ * SFSEG_ERR_STATE before a successful sfseg_power_iterate or for a batch
+ * context, SFSEG_ERR_ZERO_NORM if the iterate is zero, SFSEG_ERR_NONFINITE
+ * on non-finite values. */
+int sfseg_refine_frames(sfseg_ctx *ctx, float *x_out, double *ritz_value);
+
 /* ---- Application without allocation ------------------------------------
  * For callers that cannot allocate device memory or block: code under
  * stream capture, tight serving loops, harnesses that forbid hipMalloc.

@@ -96,6 +96,8 @@ def lib():
     L.sfseg_apply.restype = ctypes.c_int
     L.sfseg_spectral_grad.argtypes = [P, P, P, ctypes.c_int32, P, ctypes.POINTER(ctypes.c_double)]
     L.sfseg_spectral_grad.restype = ctypes.c_int
+    L.sfseg_refine_frames.argtypes = [P, P, ctypes.POINTER(ctypes.c_double)]
+    L.sfseg_refine_frames.restype = ctypes.c_int
     L.sfseg_apply_noalloc.argtypes = [P, P, P]
     L.sfseg_apply_noalloc.restype = ctypes.c_int
     L.sfseg_apply_noalloc_bytes.argtypes = [P]

@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsfseg.so")
 SOURCES = ["step_f32.hip", "step_bf16.hip", "step_f16.hip", "kernels.hip", "api.hip",
            "batch.hip", "unet.hip", "binarize.hip", "noalloc.hip",
-           "spectral.hip"]
+           "spectral.hip", "refine.hip"]
 ARCH = os.environ.get("SFSEG_OFFLOAD_ARCH", "gfx950")
 
 

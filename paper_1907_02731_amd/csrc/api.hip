@@ -104,12 +104,14 @@ void sfseg_destroy(sfseg_ctx* ctx) {
         if (e) (void)hipEventDestroy(e);
     void* dev[] = {ctx->w, ctx->f, ctx->s0, ctx->buf[0], ctx->buf[1], ctx->apply_in,
                    ctx->apply_out, ctx->st, ctx->st_apply, ctx->d_bad, ctx->partials,
-                   ctx->step_part, ctx->items, ctx->spec_buf, ctx->spec_norms, ctx->spec_part};
+                   ctx->step_part, ctx->items, ctx->spec_buf, ctx->spec_norms, ctx->spec_part,
+                   ctx->ritz_part, ctx->ritz_fac};
     for (void* p : dev)
         if (p) (void)hipFree(p);
     if (ctx->h_st) (void)hipHostFree(ctx->h_st);
     if (ctx->h_bad) (void)hipHostFree(ctx->h_bad);
     if (ctx->h_spec) (void)hipHostFree(ctx->h_spec);
+    if (ctx->h_ritz) (void)hipHostFree(ctx->h_ritz);
     delete ctx;
 }
 

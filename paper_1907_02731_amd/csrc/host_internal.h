@@ -100,4 +100,9 @@ struct sfseg_ctx {
     int spec_norms_cap = 0;
     double* spec_part = nullptr;    // sfseg_spectral_grad: block sums
     double* h_spec = nullptr;       // pinned copy of the loss sums
+    double* ritz_part = nullptr;    // sfseg_refine_frames: frame sums (block shares)
+    double* h_ritz = nullptr;       // sfseg_refine_frames: pinned copy of them / the factors
+    size_t ritz_cap = 0;            // doubles in ritz_part and h_ritz
+    double* ritz_fac = nullptr;     // sfseg_refine_frames: frame factors on the device
+    size_t ritz_fac_cap = 0;
 };

@@ -161,6 +161,41 @@ class Solver:
             torch.cuda.current_stream().wait_stream(self.stream)
         return out, float(loss.value)
 
+    def refine_frames(self, out: Optional[torch.Tensor] = None):
+        """Frame-wise Rayleigh-Ritz refinement of the current iterate
+        (sfseg_refine_frames): (unit start vector, largest Ritz value)."""
+        with torch.cuda.device(self.device):
+            if out is None:
+                with torch.cuda.stream(self.stream):
+                    out = torch.empty(self.shape, dtype=torch.float32, device=self.device)
+            po = _dev_ptr(out, "out", self.shape)
+            self.stream.wait_stream(torch.cuda.current_stream())
+            mu = ctypes.c_double()
+            _lib.check(_lib.lib().sfseg_refine_frames(self._handle(), po, ctypes.byref(mu)),
+                       "sfseg_refine_frames")
+            torch.cuda.current_stream().wait_stream(self.stream)
+        return out, float(mu.value)
+
+    def iterate_refined(self, x0: Optional[torch.Tensor] = None, pre_steps: int = 5,
+                        refinements: int = 1, between: int = 20, max_iters: int = 20000,
+                        tol: float = 1e-5):
+        """Warm-started solve: `pre_steps` plain steps from x0 (S by
+        default), the frame-wise refinement, then -- `refinements` - 1 more
+        times -- `between` plain steps and another refinement, then plain
+        steps to `tol`.  Returns (final IterResult, steps in all, Ritz values).
+        Every step and refinement runs in the library."""
+        r = self.iterate(x0, max_iters=pre_steps, tol=0.0)
+        steps = r.iters
+        mus = []
+        for i in range(refinements):
+            if i:
+                r = self.iterate(x, max_iters=between, tol=0.0)
+                steps += r.iters
+            x, mu = self.refine_frames()
+            mus.append(mu)
+        r = self.iterate(x, max_iters=max_iters, tol=tol)
+        return r, steps + r.iters, mus
+
     # -- binarisation (Sec. 4.1) ----------------------------------------------
     def _mask_out(self, out: Optional[torch.Tensor]) -> torch.Tensor:
         if out is None:

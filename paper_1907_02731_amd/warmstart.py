@@ -264,6 +264,24 @@ def solve_cold(S: torch.Tensor, tol: float = 1e-5, graph: Dict = GRAPH, max_iter
     return r, x, time.perf_counter() - t0
 
 
+def solve_refined(S: torch.Tensor, tol: float = 1e-5, graph: Dict = GRAPH,
+                  max_iters: int = 20000, plan: Optional[Tuple[int, int]] = None,
+                  pre_steps: int = 5, refinements: int = 1, between: int = 20):
+    """Plain steps from S, the frame-wise Rayleigh-Ritz refinement
+    (sfseg_refine_frames), then the plain method to the same tolerance:
+    (result, eigenvector, seconds, steps in all, Ritz values)."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with Solver(S, **graph) as sol:
+        if plan is not None:
+            sol.set_plan(*plan)
+        r, steps, mus = sol.iterate_refined(pre_steps=pre_steps, refinements=refinements,
+                                            between=between, max_iters=max_iters, tol=tol)
+        x = sol.eigvec()
+    torch.cuda.synchronize()
+    return r, x, time.perf_counter() - t0, steps, mus
+
+
 def solve_warm(S: torch.Tensor, net: UNet, tol: float = 1e-5, graph: Dict = GRAPH,
                max_iters: int = 20000, plan: Optional[Tuple[int, int]] = None):
     """Network estimate as the start vector, then the plain method to the same

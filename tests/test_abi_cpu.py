@@ -105,6 +105,7 @@ def test_null_arguments_rejected():
         _lib.SFSEG_ERR_INVALID_ARG
     assert L.sfseg_apply_noalloc_bytes(None) == 0
     assert L.sfseg_spectral_grad(None, None, None, 1, None, None) == _lib.SFSEG_ERR_INVALID_ARG
+    assert L.sfseg_refine_frames(None, None, None) == _lib.SFSEG_ERR_INVALID_ARG
     assert L.sfseg_last_timing(None, None) == _lib.SFSEG_ERR_INVALID_ARG
     b = _lib.Binarize()
     L.sfseg_binarize_default(ctypes.byref(b))

@@ -12,8 +12,8 @@ lambda_2 < rho <= lambda_1, two bounds of symmetric eigenvalue theory hold:
     Kato-Temple:   0 <= lambda_1 - rho <= r^2 / (rho - lambda_2)
     Davis-Kahan:   sin angle(x, v_1) <= r / (rho - lambda_2)
 
-The plain, batched and warm-started results (each iterated to delta < 1e-5
-on the GPU) are checked against the first -- the GPU's Rayleigh quotient
+The plain, batched, warm-started and frame-refined results (each iterated to
+delta < 1e-5 on the GPU) are checked against the first -- the GPU's Rayleigh quotient
 pinned to Lanczos' lambda_1 -- and the second gives each vector's distance to
 the true eigenvector v_1; warm and cold results must lie within the sum of
 their two bounds of each other (the same eigenvector, judged by the
@@ -117,9 +117,21 @@ def test_plain_batched_and_warm_results_are_within_the_spectral_bounds(spectrum,
             xw = sol.eigvec().cpu().numpy().astype(np.float64).ravel()
     dk_w = _check("warm start", xw, rw, mf, spectrum)
 
+    # frame-wise Rayleigh-Ritz refined start: 5 plain steps, the refinement, plain steps
+    with Solver(St, **KW) as sol:
+        _plan(sol)
+        rr, steps, mus = sol.iterate_refined(pre_steps=5, max_iters=5000, tol=TOL)
+        xr = sol.eigvec().cpu().numpy().astype(np.float64).ravel()
+    dk_r = _check("refined start", xr, rr, mf, spectrum)
+    print(f"refined start: {steps} steps in all against {rc.iters} plain; Ritz value "
+          f"{mus[0]:.10f} <= lambda_1 {lam1:.10f}", flush=True)
+    assert steps < rc.iters
+    assert mus[0] <= lam1 * (1 + 1e-12) + spectrum[2]
+
     # both ends of each pair lie within their bounds of v_1
     for (na, xa, da), (nb, xb_, db) in (((("plain", xc, dk_c)), ("warm start", xw, dk_w)),
-                                        ((("plain", xc, dk_c)), ("batched", xb, dk_b))):
+                                        ((("plain", xc, dk_c)), ("batched", xb, dk_b)),
+                                        ((("plain", xc, dk_c)), ("refined start", xr, dk_r))):
         d = float(np.linalg.norm(xa - xb_))
         print(f"||x_{nb} - x_{na}|| = {d:.3e} <= {1.01 * (da + db):.3e}", flush=True)
         assert d <= 1.01 * (da + db) + 1e-7
