@@ -189,6 +189,8 @@ def parse():
     ap.add_argument("--features", type=int, default=1, choices=[1, 2],
                     help="pairwise feature channels (2: the clip and a motion-like map, Eq. (9))")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--refine-pre-steps", type=int, default=5,
+                    help="plain steps before the frame-wise Rayleigh-Ritz refinement")
     ap.add_argument("--no-forms", action="store_true",
                     help="full workload: skip the batched and warm-start time-to-converge "
                          "measurements that the default line carries beside the plain one")
@@ -374,7 +376,7 @@ def warmstart_measure(args, reps: int = None, warmup: int = None, S_np=None) -> 
 
     from paper_1907_02731_amd.synth import full_clip
     from paper_1907_02731_amd.warmstart import (GRAPH, WEIGHTS, UNet, load_params, solve_cold,
-                                                solve_warm)
+                                                solve_refined, solve_warm)
 
     if not os.path.exists(WEIGHTS):
         raise FileNotFoundError(f"no trained weights at {WEIGHTS} (train them with "
@@ -391,26 +393,46 @@ def warmstart_measure(args, reps: int = None, warmup: int = None, S_np=None) -> 
         with Solver(S, **GRAPH) as sol:
             plan_info = sol.autotune(steps=32, cache=args.plan_cache or None)
         plan = (plan_info["shape"], plan_info["chunks"])
+    def refined(use_net):
+        return solve_refined(S, tol=args.tol, graph=GRAPH, plan=plan,
+                             pre_steps=args.refine_pre_steps, net=net if use_net else None)
+
     for _ in range(warmup):
         solve_cold(S, tol=args.tol, graph=GRAPH, plan=plan)
         solve_warm(S, net, tol=args.tol, graph=GRAPH, plan=plan)
-    cold, warm = [], []
+        refined(False)
+        refined(True)
+    cold, warm, ref, wref = [], [], [], []
     for _ in range(reps):
         cold.append(solve_cold(S, tol=args.tol, graph=GRAPH, plan=plan))
         warm.append(solve_warm(S, net, tol=args.tol, graph=GRAPH, plan=plan))
+        ref.append(refined(False))
+        wref.append(refined(True))
     net.close()
     tc = float(np.median([c[2] for c in cold]))
     tw = float(np.median([w[2] for w in warm]))
     ti = float(np.median([w[3] for w in warm]))
     rc, rw = cold[-1][0], warm[-1][0]
+    xc = cold[-1][1].cpu().numpy().astype(np.float64)
+
+    def same(r, x):
+        return {"lambda_rel_diff": abs(r.lam - rc.lam) / rc.lam,
+                "x_l2_diff": float(np.linalg.norm(x.cpu().numpy().astype(np.float64) - xc))}
+
+    def refined_entry(runs, label):
+        r = runs[-1]
+        t = float(np.median([v[2] for v in runs]))
+        return {"start": label, "pre_steps": args.refine_pre_steps, "steps": r[3],
+                "seconds": t, "speedup": tc / t, "ritz_value": r[4][0], "lambda": r[0].lam,
+                "same_eigenvector": same(r[0], r[1])}
+
     return {"shape": (T, H, W), "cold": {"steps": rc.iters, "seconds": tc, "lambda": rc.lam},
             "warm": {"steps": rw.iters, "seconds": tw, "inference_seconds": ti,
                      "lambda": rw.lam},
             "speedup": tc / tw, "steps_saved": rc.iters - rw.iters, "autotune": plan_info,
-            "same_eigenvector": {"lambda_rel_diff": abs(rw.lam - rc.lam) / rc.lam,
-                                 "x_l2_diff": float(np.linalg.norm(
-                                     warm[-1][1].cpu().numpy().astype(np.float64) -
-                                     cold[-1][1].cpu().numpy().astype(np.float64)))}}
+            "same_eigenvector": same(rw, warm[-1][1]),
+            "refined": refined_entry(ref, "S"),
+            "warm_refined": refined_entry(wref, "network estimate")}
 
 
 def bench_warmstart(args):
@@ -434,6 +456,7 @@ def bench_warmstart(args):
         "cold": m["cold"], "warm": m["warm"], "speedup": m["speedup"],
         "steps_saved": m["steps_saved"], "autotune": m["autotune"],
         "same_eigenvector": m["same_eigenvector"],
+        "refined_start": m["refined"], "warm_start_refined": m["warm_refined"],
     }
     print(json.dumps(line), flush=True)
 
@@ -673,12 +696,18 @@ def main():
         ttc["warm_start_inference"] = w["warm"]["inference_seconds"] * 1e3
         ttc["cold_start_same_run"] = w["cold"]["seconds"] * 1e3
         ttc["warm_start_speedup"] = w["speedup"]
+        ttc["refined_start"] = w["refined"]["seconds"] * 1e3
+        ttc["refined_start_speedup"] = w["refined"]["speedup"]
+        ttc["warm_start_refined"] = w["warm_refined"]["seconds"] * 1e3
+        ttc["warm_start_refined_speedup"] = w["warm_refined"]["speedup"]
         ttc["batched_24_clips"] = b["t_batch"] * 1e3
         ttc["plain_24_clips_one_by_one"] = b["t_plain"] * 1e3
         ttc["batched_speedup"] = b["t_plain"] / b["t_batch"]
         line["forms"] = {
             "warm_start": {"cold": w["cold"], "warm": w["warm"], "steps_saved": w["steps_saved"],
                            "same_eigenvector": w["same_eigenvector"]},
+            "refined_start": w["refined"],
+            "warm_start_refined": w["warm_refined"],
             "batched": {"clips": len(b["shapes"]), "voxels": b["voxels"],
                         "iters_per_clip": b["iters"], "plain_iters_per_clip": b["plain_iters"],
                         "plan": b["plan"],

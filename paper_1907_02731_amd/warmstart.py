@@ -266,16 +266,19 @@ def solve_cold(S: torch.Tensor, tol: float = 1e-5, graph: Dict = GRAPH, max_iter
 
 def solve_refined(S: torch.Tensor, tol: float = 1e-5, graph: Dict = GRAPH,
                   max_iters: int = 20000, plan: Optional[Tuple[int, int]] = None,
-                  pre_steps: int = 5, refinements: int = 1, between: int = 20):
-    """Plain steps from S, the frame-wise Rayleigh-Ritz refinement
-    (sfseg_refine_frames), then the plain method to the same tolerance:
-    (result, eigenvector, seconds, steps in all, Ritz values)."""
+                  pre_steps: int = 5, refinements: int = 1, between: int = 20,
+                  net: Optional[UNet] = None):
+    """Plain steps from S (or from the network's estimate, `net`), the
+    frame-wise Rayleigh-Ritz refinement (sfseg_refine_frames), then the plain
+    method to the same tolerance: (result, eigenvector, seconds, steps in all,
+    Ritz values); the seconds include the network's inference."""
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    x0 = net.forward(S) if net is not None else None
     with Solver(S, **graph) as sol:
         if plan is not None:
             sol.set_plan(*plan)
-        r, steps, mus = sol.iterate_refined(pre_steps=pre_steps, refinements=refinements,
+        r, steps, mus = sol.iterate_refined(x0, pre_steps=pre_steps, refinements=refinements,
                                             between=between, max_iters=max_iters, tol=tol)
         x = sol.eigvec()
     torch.cuda.synchronize()
