@@ -97,16 +97,30 @@ int grid_for(int64_t n, int per = 256) {
     return (int)std::min<int64_t>(std::max<int64_t>(b, 1), 65535 * 8);
 }
 
+// Block shape of the streamed convolution (rows RB x voxels XB): a frame
+// slab, (RB + 2) rows x (XB + 2) voxels x CIN channels of 2 bytes, is about
+// 13 KB up to 48 channels (a ring of four: three or four blocks per CU), 17 KB
+// for 64 and 26 KB for 96.  Frame runs per tile: enough blocks to give every
+// CU several.
+constexpr int conv_rows(int cin) { return cin <= 32 ? 4 : 2; }
+constexpr int conv_xb(int cin) { return cin <= 16 ? 64 : 32; }
+int conv_runs(int64_t tiles, int T) {
+    const int64_t want = 2048;
+    int64_t r = (want + tiles - 1) / tiles;
+    if (r > T) r = T;
+    return (int)(r < 1 ? 1 : r);
+}
+
 hipError_t conv_fwd(int cin, int cout, View in, View out, const bf16x8* frag, const float* bias,
                     View mask, int mode, hipStream_t s) {
     using namespace sfseg::unet;
-    const int tiles_x = (out.W + 16 * CONV_MT - 1) / (16 * CONV_MT);
-    const int64_t waves = (int64_t)out.T * out.H * tiles_x;
-    const dim3 grid((unsigned)((waves + CONV_WAVES - 1) / CONV_WAVES)), block(64 * CONV_WAVES);
 #define SFSEG_CONV_CASE(CI, CO)                                                                   \
     if (cin == CI && cout == CO) {                                                                \
-        hipLaunchKernelGGL((conv3_mfma<CI, CO>), grid, block, 0, s, in, out, frag, bias, mask,   \
-                           mode);                                                                 \
+        constexpr int RB = conv_rows(CI), XB = conv_xb(CI);                                       \
+        const int64_t tiles = (int64_t)((out.H + RB - 1) / RB) * ((out.W + XB - 1) / XB);         \
+        const int runs = conv_runs(tiles, out.T);                                                 \
+        hipLaunchKernelGGL((conv3_stream<CI, CO, RB, XB>), dim3((unsigned)(tiles * runs)),        \
+                           dim3(256), 0, s, in, out, frag, bias, mask, mode, runs);               \
         return hipGetLastError();                                                                 \
     }
     SFSEG_CONV_CASE(16, 16)

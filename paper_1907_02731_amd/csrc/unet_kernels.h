@@ -134,6 +134,175 @@ __global__ __launch_bounds__(64 * CONV_WAVES) void conv3_mfma(View in, View out,
     }
 }
 
+// The same product with the input staged in LDS and streamed along t.  A
+// block (four waves) owns RB output rows (y0 .. y0 + RB - 1) x XB voxels
+// (x0 .. x0 + XB - 1) x all COUT channels over a run of output frames
+// [ta, tb): NT = RB XB / 16 tiles of 16 voxels per frame, wave w taking the
+// MT = NT / 4 consecutive tiles from w MT (row-major over the block's rows).
+// LDS holds a ring of four frame slabs; slab slot s % 4 holds input frame s:
+// rows y0-1 .. y0+RB, voxels x0-1 .. x0+XB, all CIN channels (zeros outside
+// the volume), as 16-byte units of 8 channels laid out [row][channel
+// group][voxel], so that the 16 lanes of a lane group, which read 16
+// consecutive voxels of one channel group for one tap, read 256 contiguous
+// bytes.  For output frame t the products read slots t-1, t, t+1 while the
+// loads of frame t+2 are in flight into registers; they are written to slot
+// t+2 (which held t-2) after the products, then one barrier.  Each input
+// value thus leaves global memory about (RB + 2) / RB times per block row
+// instead of once per tap.
+template <int CIN, int COUT, int RB, int XB>
+struct ConvLds {
+    static constexpr int NCG = CIN / 8;     // 8-channel groups
+    static constexpr int ROWS = RB + 2;
+    static constexpr int VOX = XB + 2;      // outputs plus one voxel each side
+    static constexpr int UNITS = ROWS * NCG * VOX;  // 16-byte units per frame slab
+    static constexpr int PER = (UNITS + 255) / 256; // units per thread
+    static constexpr int TPR = XB / 16;     // tiles per row
+    static constexpr int MT = RB * TPR / 4; // tiles per wave
+    static_assert(MT >= 1 && TPR % MT == 0, "a wave's tiles lie in one row");
+};
+
+template <int CIN, int COUT, int RB, int XB>
+__global__ __launch_bounds__(256) void conv3_stream(View in, View out,
+                                                     const bf16x8* __restrict__ frag,
+                                                     const float* __restrict__ bias, View mask,
+                                                     int mode, int runs) {
+    using G = ConvLds<CIN, COUT, RB, XB>;
+    constexpr int NB = COUT / 16;
+    constexpr int NQ = (27 * CIN + 31) / 32;
+    constexpr int NCG = G::NCG, VOX = G::VOX, MT = G::MT, UNITS = G::UNITS, PER = G::PER;
+    static_assert(CIN % 8 == 0 && COUT % 16 == 0, "channel blocking");
+    static_assert(4 * UNITS < (1 << 24), "slab offsets fit 24 bits");
+    __shared__ u32x4_t slab[4][UNITS];
+    // For output frame t (phase t % 4), K chunk q and lane group g: the unit
+    // index in the ring of the chunk's input frame, row and voxel shift.  Past
+    // the last tap the fragments hold zeros, and the index points at frame
+    // t's own slot, which always holds loaded (finite) values: a slot not yet
+    // written could hold any bits, and 0 * NaN is NaN.
+    __shared__ int koff[4][NQ * 4];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int T = out.T, H = out.H, W = out.W;
+    const int tiles_x = (W + XB - 1) / XB;
+    const int rows_y = (H + RB - 1) / RB;
+    int b = blockIdx.x;
+    const int tx = b % tiles_x;
+    b /= tiles_x;
+    const int ty = b % rows_y;
+    const int run = b / rows_y;
+    const int ta = (int)((int64_t)T * run / runs), tb = (int)((int64_t)T * (run + 1) / runs);
+    const int x0 = tx * XB, y0 = ty * RB;
+    const u32x4_t zero = {0u, 0u, 0u, 0u};
+
+    // This thread's units of a frame slab, unit u = (r * NCG + cg) * VOX + v:
+    // their element offsets inside an input frame (-1 outside the picture).
+    int64_t uoff[PER];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const int u = j * 256 + threadIdx.x;
+        const int v = u % VOX, rest = u / VOX;
+        const int cg = rest % NCG, r = rest / NCG;
+        const int ys = y0 + r - 1, xs = x0 + v - 1;
+        uoff[j] = (u < UNITS && ys >= 0 && ys < H && xs >= 0 && xs < W)
+                      ? ((int64_t)ys * W + xs) * in.cs + in.c0 + 8 * cg
+                      : -1;
+    }
+    const int64_t fstride = (int64_t)H * W * in.cs;
+    auto load_frame = [&](int ts, u32x4_t* reg) {
+        const bool tin = ts >= 0 && ts < T;
+        const __bf16* fb = in.p + (tin ? (int64_t)ts * fstride : 0);
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            u32x4_t val = zero;
+            if (tin && uoff[j] >= 0) val = *reinterpret_cast<const u32x4_t*>(fb + uoff[j]);
+            reg[j] = val;
+        }
+    };
+    auto store_slot = [&](int ts, const u32x4_t* reg) {
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int u = j * 256 + threadIdx.x;
+            if (u < UNITS) slab[ts & 3][u] = reg[j];
+        }
+    };
+    for (int e = threadIdx.x; e < 4 * NQ * 4; e += 256) {
+        const int ph = e / (NQ * 4), qg = e - ph * (NQ * 4);
+        const int k = 32 * (qg >> 2) + 8 * (qg & 3);
+        const int tap = k / CIN, c = k - tap * CIN;
+        koff[ph][qg] = tap < 27 ? ((ph + 3 + tap / 9) & 3) * UNITS +
+                                      (((tap / 3) % 3) * NCG + c / 8) * VOX + tap % 3
+                                : ph * UNITS;
+    }
+    {
+        u32x4_t reg[PER];
+        for (int ts = ta - 1; ts <= ta + 1; ++ts) {
+            load_frame(ts, reg);
+            store_slot(ts, reg);
+        }
+    }
+    __syncthreads();
+
+    const int tile0 = wave * MT;
+    const int row = tile0 / G::TPR;          // output row inside the block
+    const int v0 = 16 * (tile0 % G::TPR);    // first output voxel of the wave in the row
+    const int y = y0 + row;
+    const int i = lane & 15, g = lane >> 4;
+    for (int t = ta; t < tb; ++t) {
+        // the fragments are re-read every frame (from L1), not held in
+        // registers across frames
+        const bf16x8* fr = frag;
+        asm volatile("" : "+s"(fr));
+        u32x4_t next[PER];
+        load_frame(t + 2, next);  // consumed after this frame's products
+        f32x4 acc[MT][NB];
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+            for (int n = 0; n < NB; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+        const u32x4_t* sl = &slab[0][0] + (row * NCG * VOX + v0 + i);
+        const int* kt = &koff[t & 3][g];
+#pragma unroll 4
+        for (int q = 0; q < NQ; ++q) {
+            bf16x8 bf[NB];
+#pragma unroll
+            for (int n = 0; n < NB; ++n) bf[n] = fr[((int64_t)q * NB + n) * 64 + lane];
+            const u32x4_t* sp = sl + kt[4 * q];
+#pragma unroll
+            for (int m = 0; m < MT; ++m) {
+                const u32x4_t a4 = sp[16 * m];
+                const bf16x8 a = __builtin_bit_cast(bf16x8, a4);
+#pragma unroll
+                for (int n = 0; n < NB; ++n)
+                    acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bf[n], acc[m][n], 0, 0, 0);
+            }
+        }
+        if (y < H) {
+            const int64_t obase = ((int64_t)t * H + y) * W;
+#pragma unroll
+            for (int m = 0; m < MT; ++m) {
+#pragma unroll
+                for (int rr = 0; rr < 4; ++rr) {
+                    const int xo = x0 + v0 + 16 * m + 4 * g + rr;
+                    if (xo >= W) continue;
+                    const int64_t v = obase + xo;
+#pragma unroll
+                    for (int n = 0; n < NB; ++n) {
+                        const int co = 16 * n + i;
+                        float val = acc[m][n][rr];
+                        if (mode == 0) {
+                            val = fmaxf(val + bias[co], 0.f);
+                        } else if (mask.p) {
+                            if (!((float)mask.p[v * mask.cs + mask.c0 + co] > 0.f)) val = 0.f;
+                        }
+                        out.p[v * out.cs + out.c0 + co] = (__bf16)val;
+                    }
+                }
+            }
+        }
+        store_slot(t + 2, next);  // slot of frame t - 2, read by no one now
+        __syncthreads();
+    }
+}
+
 // First layer: one FP32 input channel, K = the 27 taps (one chunk of 32, the
 // last 5 zero).  Lane group g reads taps 8 g .. 8 g + 7 of its voxel.
 template <int COUT>
