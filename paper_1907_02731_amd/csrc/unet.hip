@@ -377,22 +377,22 @@ int sfseg_unet_forward(sfseg_unet* n, const float* S, int32_t T, int32_t H, int3
         HIP_TRY(hipGetLastError());
     }
     HIP_TRY(conv_fwd(16, 16, e1a, e1, n->ffwd[ENC1B], bias(ENC1B), none, 0, s));
-    hipLaunchKernelGGL(sfseg::unet::pool2_fwd, dim3(grid_for((int64_t)Th * Hh * Wh * 16)), dim3(256), 0,
+    hipLaunchKernelGGL(sfseg::unet::pool2_fwd, dim3(grid_for((int64_t)Th * Hh * Wh * 2)), dim3(256), 0,
                        s, e1, p1, 16);
     HIP_TRY(hipGetLastError());
     HIP_TRY(conv_fwd(16, 32, p1, e2a, n->ffwd[ENC2A], bias(ENC2A), none, 0, s));
     HIP_TRY(conv_fwd(32, 32, e2a, e2, n->ffwd[ENC2B], bias(ENC2B), none, 0, s));
-    hipLaunchKernelGGL(sfseg::unet::pool2_fwd, dim3(grid_for((int64_t)Tq * Hq * Wq * 32)), dim3(256), 0,
+    hipLaunchKernelGGL(sfseg::unet::pool2_fwd, dim3(grid_for((int64_t)Tq * Hq * Wq * 4)), dim3(256), 0,
                        s, e2, p2, 32);
     HIP_TRY(hipGetLastError());
     HIP_TRY(conv_fwd(32, 64, p2, ba, n->ffwd[BOTA], bias(BOTA), none, 0, s));
     HIP_TRY(conv_fwd(64, 64, ba, bb, n->ffwd[BOTB], bias(BOTB), none, 0, s));
-    hipLaunchKernelGGL(sfseg::unet::up2_fwd, dim3(grid_for((int64_t)Th * Hh * Wh * 64)), dim3(256), 0,
+    hipLaunchKernelGGL(sfseg::unet::up2_fwd, dim3(grid_for((int64_t)Th * Hh * Wh * 8)), dim3(256), 0,
                        s, bb, u2, 64);
     HIP_TRY(hipGetLastError());
     HIP_TRY(conv_fwd(96, 32, cat2, d2a, n->ffwd[DEC2A], bias(DEC2A), none, 0, s));
     HIP_TRY(conv_fwd(32, 32, d2a, d2, n->ffwd[DEC2B], bias(DEC2B), none, 0, s));
-    hipLaunchKernelGGL(sfseg::unet::up2_fwd, dim3(grid_for(nv * 32)), dim3(256), 0, s, d2, u1, 32);
+    hipLaunchKernelGGL(sfseg::unet::up2_fwd, dim3(grid_for(nv * 4)), dim3(256), 0, s, d2, u1, 32);
     HIP_TRY(hipGetLastError());
     HIP_TRY(conv_fwd(48, 16, cat1, d1a, n->ffwd[DEC1A], bias(DEC1A), none, 0, s));
     HIP_TRY(conv_fwd(16, 16, d1a, d1, n->ffwd[DEC1B], bias(DEC1B), none, 0, s));

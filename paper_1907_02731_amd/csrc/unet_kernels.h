@@ -29,6 +29,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <utility>
+
 namespace sfseg {
 namespace unet {
 
@@ -149,6 +151,29 @@ __global__ __launch_bounds__(64 * CONV_WAVES) void conv3_mfma(View in, View out,
 // t+2 (which held t-2) after the products, then one barrier.  Each input
 // value thus leaves global memory about (RB + 2) / RB times per block row
 // instead of once per tap.
+// K chunk Q of the product (k = 32 Q .. 32 Q + 31, k = tap * CIN + channel):
+// lane group g holds k = 32 Q + 8 g .. + 7.  The chunk starts on tap tl; lane
+// groups g >= gs are on the next tap th (gs = 4: none).  For each of the two
+// taps, the input frame f (0..2 for t-1 .. t+1) and the unit offset inside a
+// frame slab relative to the lane's base ((row * NCG + g) * VOX + voxel):
+// row shift dy, channel group, voxel shift dx.  Past the last tap the
+// fragments hold zeros and the offsets point at loaded values of frame t.
+template <int CIN, int NCG, int VOX, int Q>
+struct ConvChunk {
+    static constexpr int k0 = 32 * Q;
+    static constexpr int tl = k0 / CIN, th = (k0 + 31) / CIN;
+    static constexpr int gs = th == tl ? 4 : (CIN * th - k0) / 8;
+    static constexpr int fl = tl < 27 ? tl / 9 : 1;
+    static constexpr int ol = tl < 27 ? (((tl / 3) % 3) * NCG + (k0 - CIN * tl) / 8) * VOX + tl % 3 : 0;
+    static constexpr int fh = th < 27 ? th / 9 : 1;
+    static constexpr int oh = th < 27 ? (((th / 3) % 3) * NCG - gs) * VOX + th % 3 : -gs * VOX;
+};
+
+template <typename F, int... Qs>
+__device__ __forceinline__ void for_each_chunk(F&& f, std::integer_sequence<int, Qs...>) {
+    (f(std::integral_constant<int, Qs>{}), ...);
+}
+
 template <int CIN, int COUT, int RB, int XB>
 struct ConvLds {
     static constexpr int NCG = CIN / 8;     // 8-channel groups
@@ -171,14 +196,7 @@ __global__ __launch_bounds__(256) void conv3_stream(View in, View out,
     constexpr int NQ = (27 * CIN + 31) / 32;
     constexpr int NCG = G::NCG, VOX = G::VOX, MT = G::MT, UNITS = G::UNITS, PER = G::PER;
     static_assert(CIN % 8 == 0 && COUT % 16 == 0, "channel blocking");
-    static_assert(4 * UNITS < (1 << 24), "slab offsets fit 24 bits");
     __shared__ u32x4_t slab[4][UNITS];
-    // For output frame t (phase t % 4), K chunk q and lane group g: the unit
-    // index in the ring of the chunk's input frame, row and voxel shift.  Past
-    // the last tap the fragments hold zeros, and the index points at frame
-    // t's own slot, which always holds loaded (finite) values: a slot not yet
-    // written could hold any bits, and 0 * NaN is NaN.
-    __shared__ int koff[4][NQ * 4];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int T = out.T, H = out.H, W = out.W;
@@ -224,14 +242,6 @@ __global__ __launch_bounds__(256) void conv3_stream(View in, View out,
             if (u < UNITS) slab[ts & 3][u] = reg[j];
         }
     };
-    for (int e = threadIdx.x; e < 4 * NQ * 4; e += 256) {
-        const int ph = e / (NQ * 4), qg = e - ph * (NQ * 4);
-        const int k = 32 * (qg >> 2) + 8 * (qg & 3);
-        const int tap = k / CIN, c = k - tap * CIN;
-        koff[ph][qg] = tap < 27 ? ((ph + 3 + tap / 9) & 3) * UNITS +
-                                      (((tap / 3) % 3) * NCG + c / 8) * VOX + tap % 3
-                                : ph * UNITS;
-    }
     {
         u32x4_t reg[PER];
         for (int ts = ta - 1; ts <= ta + 1; ++ts) {
@@ -246,11 +256,17 @@ __global__ __launch_bounds__(256) void conv3_stream(View in, View out,
     const int v0 = 16 * (tile0 % G::TPR);    // first output voxel of the wave in the row
     const int y = y0 + row;
     const int i = lane & 15, g = lane >> 4;
+    // Weight fragments: held in registers for the whole run where they fit
+    // (4 NQ NB registers), else re-read from L1 / L2 for every frame.
+    constexpr bool BREG = NQ * NB <= 42;
+    bf16x8 breg[BREG ? NQ : 1][NB];
+    if constexpr (BREG) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+#pragma unroll
+            for (int n = 0; n < NB; ++n) breg[q][n] = frag[(q * NB + n) * 64 + lane];
+    }
     for (int t = ta; t < tb; ++t) {
-        // the fragments are re-read every frame (from L1), not held in
-        // registers across frames
-        const bf16x8* fr = frag;
-        asm volatile("" : "+s"(fr));
         u32x4_t next[PER];
         load_frame(t + 2, next);  // consumed after this frame's products
         f32x4 acc[MT][NB];
@@ -258,22 +274,38 @@ __global__ __launch_bounds__(256) void conv3_stream(View in, View out,
         for (int m = 0; m < MT; ++m)
 #pragma unroll
             for (int n = 0; n < NB; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
-        const u32x4_t* sl = &slab[0][0] + (row * NCG * VOX + v0 + i);
-        const int* kt = &koff[t & 3][g];
-#pragma unroll 4
-        for (int q = 0; q < NQ; ++q) {
-            bf16x8 bf[NB];
-#pragma unroll
-            for (int n = 0; n < NB; ++n) bf[n] = fr[((int64_t)q * NB + n) * 64 + lane];
-            const u32x4_t* sp = sl + kt[4 * q];
+        // the lane's base in the slabs of frames t-1, t, t+1 (all loaded)
+        const int lane_off = (row * NCG + g) * VOX + v0 + i;
+        const u32x4_t* fb[3] = {&slab[(t + 3) & 3][lane_off], &slab[t & 3][lane_off],
+                                &slab[(t + 1) & 3][lane_off]};
+        auto chunk = [&](auto qc, const bf16x8* bf) {
+            using C = ConvChunk<CIN, NCG, VOX, decltype(qc)::value>;
+            const u32x4_t* sp =
+                (C::gs == 4 || g < C::gs) ? fb[C::fl] + C::ol : fb[C::fh] + C::oh;
 #pragma unroll
             for (int m = 0; m < MT; ++m) {
-                const u32x4_t a4 = sp[16 * m];
-                const bf16x8 a = __builtin_bit_cast(bf16x8, a4);
+                const bf16x8 a = __builtin_bit_cast(bf16x8, sp[16 * m]);
 #pragma unroll
                 for (int n = 0; n < NB; ++n)
                     acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bf[n], acc[m][n], 0, 0, 0);
             }
+        };
+        if constexpr (BREG) {
+            for_each_chunk([&](auto qc) { chunk(qc, breg[decltype(qc)::value]); },
+                           std::make_integer_sequence<int, NQ>{});
+        } else {
+            // re-read every frame, not hoisted out of the frame loop
+            const bf16x8* fr = frag;
+            asm volatile("" : "+s"(fr));
+            for_each_chunk(
+                [&](auto qc) {
+                    constexpr int q = decltype(qc)::value;
+                    bf16x8 bf[NB];
+#pragma unroll
+                    for (int n = 0; n < NB; ++n) bf[n] = fr[(q * NB + n) * 64 + lane];
+                    chunk(qc, bf);
+                },
+                std::make_integer_sequence<int, NQ>{});
         }
         if (y < H) {
             const int64_t obase = ((int64_t)t * H + y) * W;
@@ -525,21 +557,29 @@ __global__ void sum_partials(const double* __restrict__ part, int blocks, int C,
 // ---------------------------------------------------------------------------
 // out (ceil sizes) = 2x2x2 average of in over a zero-padded window.
 __global__ void pool2_fwd(View in, View out, int C) {
-    const int64_t n = (int64_t)out.T * out.H * out.W * C;
+    // one thread per (output voxel, 8 channels): 16-byte loads and stores
+    const int C8 = C / 8;
+    const int64_t n = (int64_t)out.T * out.H * out.W * C8;
     for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n;
          idx += (int64_t)gridDim.x * blockDim.x) {
-        const int c = (int)(idx % C);
-        const int64_t v = idx / C;
+        const int c = 8 * (int)(idx % C8);
+        const int64_t v = idx / C8;
         const int xo = (int)(v % out.W), yo = (int)((v / out.W) % out.H), to = (int)(v / ((int64_t)out.W * out.H));
-        float s = 0.f;
+        float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         for (int a = 0; a < 2; ++a)
             for (int b = 0; b < 2; ++b)
                 for (int d = 0; d < 2; ++d) {
                     const int t = 2 * to + a, y = 2 * yo + b, x = 2 * xo + d;
-                    if (t < in.T && y < in.H && x < in.W)
-                        s += (float)in.p[(((int64_t)t * in.H + y) * in.W + x) * in.cs + in.c0 + c];
+                    if (t < in.T && y < in.H && x < in.W) {
+                        const bf16x8 q = load8(in.p + (((int64_t)t * in.H + y) * in.W + x) * in.cs + in.c0 + c);
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) s[e] += (float)q[e];
+                    }
                 }
-        out.p[v * out.cs + out.c0 + c] = (__bf16)(s * 0.125f);
+        bf16x8 o;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) o[e] = (__bf16)(s[e] * 0.125f);
+        *reinterpret_cast<u32x4_t*>(out.p + v * out.cs + out.c0 + c) = __builtin_bit_cast(u32x4_t, o);
     }
 }
 
@@ -561,14 +601,17 @@ __global__ void pool2_bwd(View gout, View skip, View act, View gin, int C) {
 
 // out[v] = in[parent(v)] (nearest 2x, cropped to out's size).
 __global__ void up2_fwd(View in, View out, int C) {
-    const int64_t n = (int64_t)out.T * out.H * out.W * C;
+    // one thread per (output voxel, 8 channels): 16-byte loads and stores
+    const int C8 = C / 8;
+    const int64_t n = (int64_t)out.T * out.H * out.W * C8;
     for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n;
          idx += (int64_t)gridDim.x * blockDim.x) {
-        const int c = (int)(idx % C);
-        const int64_t v = idx / C;
+        const int c = 8 * (int)(idx % C8);
+        const int64_t v = idx / C8;
         const int x = (int)(v % out.W), y = (int)((v / out.W) % out.H), t = (int)(v / ((int64_t)out.W * out.H));
         const int64_t pv = ((int64_t)(t >> 1) * in.H + (y >> 1)) * in.W + (x >> 1);
-        out.p[v * out.cs + out.c0 + c] = in.p[pv * in.cs + in.c0 + c];
+        *reinterpret_cast<u32x4_t*>(out.p + v * out.cs + out.c0 + c) =
+            *reinterpret_cast<const u32x4_t*>(in.p + pv * in.cs + in.c0 + c);
     }
 }
 
