@@ -98,12 +98,12 @@ int grid_for(int64_t n, int per = 256) {
 }
 
 // Block shape of the streamed convolution (rows RB x voxels XB): a frame
-// slab, (RB + 2) rows x (XB + 2) voxels x CIN channels of 2 bytes, is about
-// 13 KB up to 48 channels (a ring of four: three or four blocks per CU), 17 KB
-// for 64 and 26 KB for 96.  Frame runs per tile: enough blocks to give every
+// slab, (RB + 2) rows x (XB + 2) voxels x CIN channels of 2 bytes, is 6.5 KB
+// for 16 channels, 13 KB for 32 and 48 (a ring of four: three blocks per CU),
+// 17 KB for 64 and 26 KB for 96.  Frame runs per tile: enough blocks to give every
 // CU several.
 constexpr int conv_rows(int cin) { return cin <= 32 ? 4 : 2; }
-constexpr int conv_xb(int cin) { return cin <= 16 ? 64 : 32; }
+constexpr int conv_xb(int) { return 32; }
 int conv_runs(int64_t tiles, int T) {
     const int64_t want = 2048;
     int64_t r = (want + tiles - 1) / tiles;
