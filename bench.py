@@ -189,7 +189,7 @@ def parse():
     ap.add_argument("--features", type=int, default=1, choices=[1, 2],
                     help="pairwise feature channels (2: the clip and a motion-like map, Eq. (9))")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--refine-pre-steps", type=int, default=0,
+    ap.add_argument("--refine-pre-steps", type=int, default=5,
                     help="plain steps before the frame-wise Rayleigh-Ritz refinement")
     ap.add_argument("--no-forms", action="store_true",
                     help="full workload: skip the batched and warm-start time-to-converge "

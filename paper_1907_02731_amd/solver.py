@@ -176,7 +176,7 @@ class Solver:
             torch.cuda.current_stream().wait_stream(self.stream)
         return out, float(mu.value)
 
-    def iterate_refined(self, x0: Optional[torch.Tensor] = None, pre_steps: int = 0,
+    def iterate_refined(self, x0: Optional[torch.Tensor] = None, pre_steps: int = 5,
                         refinements: int = 1, between: int = 20, max_iters: int = 20000,
                         tol: float = 1e-5):
         """Warm-started solve: `pre_steps` plain steps from x0 (S by

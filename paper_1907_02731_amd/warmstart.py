@@ -266,7 +266,7 @@ def solve_cold(S: torch.Tensor, tol: float = 1e-5, graph: Dict = GRAPH, max_iter
 
 def solve_refined(S: torch.Tensor, tol: float = 1e-5, graph: Dict = GRAPH,
                   max_iters: int = 20000, plan: Optional[Tuple[int, int]] = None,
-                  pre_steps: int = 0, refinements: int = 1, between: int = 20,
+                  pre_steps: int = 5, refinements: int = 1, between: int = 20,
                   net: Optional[UNet] = None):
     """Plain steps from S (or from the network's estimate, `net`), the
     frame-wise Rayleigh-Ritz refinement (sfseg_refine_frames), then the plain

@@ -117,10 +117,10 @@ def test_plain_batched_and_warm_results_are_within_the_spectral_bounds(spectrum,
             xw = sol.eigvec().cpu().numpy().astype(np.float64).ravel()
     dk_w = _check("warm start", xw, rw, mf, spectrum)
 
-    # frame-wise Rayleigh-Ritz refined start: the refinement of S, then plain steps
+    # frame-wise Rayleigh-Ritz refined start: 5 plain steps, the refinement, plain steps
     with Solver(St, **KW) as sol:
         _plan(sol)
-        rr, steps, mus = sol.iterate_refined(max_iters=5000, tol=TOL)
+        rr, steps, mus = sol.iterate_refined(pre_steps=5, max_iters=5000, tol=TOL)
         xr = sol.eigvec().cpu().numpy().astype(np.float64).ravel()
     dk_r = _check("refined start", xr, rr, mf, spectrum)
     print(f"refined start: {steps} steps in all against {rc.iters} plain; Ritz value "
