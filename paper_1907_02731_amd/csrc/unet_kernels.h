@@ -249,6 +249,11 @@ __global__ __launch_bounds__(256) void conv3_stream(View in, View out,
             store_slot(ts, reg);
         }
     }
+    // Loads run PD frames ahead of their slot: with PD = 2 the values of frame
+    // t + 2 arrive during frame t - 1 and wait in `ahead` (registers allowing).
+    constexpr int PD = (NQ * NB <= 42 && NQ * NB > 28) ? 1 : 2;
+    u32x4_t ahead[PD == 2 ? PER : 1];
+    if constexpr (PD == 2) load_frame(ta + 2, ahead);
     __syncthreads();
 
     const int tile0 = wave * MT;
@@ -268,7 +273,8 @@ __global__ __launch_bounds__(256) void conv3_stream(View in, View out,
     }
     for (int t = ta; t < tb; ++t) {
         u32x4_t next[PER];
-        load_frame(t + 2, next);  // consumed after this frame's products
+        load_frame(t + 1 + PD, next);  // consumed after this frame's products (PD = 1)
+                                       // or the next frame's (PD = 2)
         f32x4 acc[MT][NB];
 #pragma unroll
         for (int m = 0; m < MT; ++m)
@@ -330,7 +336,14 @@ __global__ __launch_bounds__(256) void conv3_stream(View in, View out,
                 }
             }
         }
-        store_slot(t + 2, next);  // slot of frame t - 2, read by no one now
+        // slot of frame t - 2, read by no one now
+        if constexpr (PD == 2) {
+            store_slot(t + 2, ahead);
+#pragma unroll
+            for (int j = 0; j < PER; ++j) ahead[j] = next[j];
+        } else {
+            store_slot(t + 2, next);
+        }
         __syncthreads();
     }
 }
