@@ -197,6 +197,9 @@ __global__ __launch_bounds__(256) void conv3_stream(View in, View out,
     constexpr int NCG = G::NCG, VOX = G::VOX, MT = G::MT, UNITS = G::UNITS, PER = G::PER;
     static_assert(CIN % 8 == 0 && COUT % 16 == 0, "channel blocking");
     __shared__ u32x4_t slab[4][UNITS];
+    // Output staging: each wave's tiles as [tile][voxel][16 channels] bf16, so
+    // that the stores to the channels-last output are 16 bytes per lane.
+    __shared__ __bf16 obuf[4][MT * NB][16 * 16];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int T = out.T, H = out.H, W = out.W;
@@ -313,26 +316,44 @@ __global__ __launch_bounds__(256) void conv3_stream(View in, View out,
                 },
                 std::make_integer_sequence<int, NQ>{});
         }
+        // bias and ReLU in the accumulator layout (lane: channel i, voxels
+        // 4 g .. 4 g + 3), through LDS into [voxel][channel], then 16-byte
+        // stores of 8 channels, the mask applied on those
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+            for (int n = 0; n < NB; ++n) {
+                const float bco = mode == 0 ? bias[16 * n + i] : 0.f;
+#pragma unroll
+                for (int rr = 0; rr < 4; ++rr) {
+                    float val = acc[m][n][rr];
+                    if (mode == 0) val = fmaxf(val + bco, 0.f);
+                    obuf[wave][m * NB + n][(4 * g + rr) * 16 + i] = (__bf16)val;
+                }
+            }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         if (y < H) {
             const int64_t obase = ((int64_t)t * H + y) * W;
 #pragma unroll
-            for (int m = 0; m < MT; ++m) {
-#pragma unroll
-                for (int rr = 0; rr < 4; ++rr) {
-                    const int xo = x0 + v0 + 16 * m + 4 * g + rr;
-                    if (xo >= W) continue;
+            for (int c0 = 0; c0 < MT * NB * 32; c0 += 64) {
+                const int c = c0 + lane;
+                const int tl = c >> 5, vv = (c & 31) >> 1, half = c & 1;
+                const int m = tl / NB, n = tl - m * NB;
+                const int xo = x0 + v0 + 16 * m + vv;
+                if (c < MT * NB * 32 && xo < W) {
                     const int64_t v = obase + xo;
+                    u32x4_t o = *reinterpret_cast<const u32x4_t*>(&obuf[wave][tl][vv * 16 + 8 * half]);
+                    if (mode != 0 && mask.p) {
+                        const bf16x8 mk = load8(mask.p + v * mask.cs + mask.c0 + 16 * n + 8 * half);
+                        bf16x8 ov = __builtin_bit_cast(bf16x8, o);
 #pragma unroll
-                    for (int n = 0; n < NB; ++n) {
-                        const int co = 16 * n + i;
-                        float val = acc[m][n][rr];
-                        if (mode == 0) {
-                            val = fmaxf(val + bias[co], 0.f);
-                        } else if (mask.p) {
-                            if (!((float)mask.p[v * mask.cs + mask.c0 + co] > 0.f)) val = 0.f;
-                        }
-                        out.p[v * out.cs + out.c0 + co] = (__bf16)val;
+                        for (int e = 0; e < 8; ++e)
+                            if (!((float)mk[e] > 0.f)) ov[e] = (__bf16)0.f;
+                        o = __builtin_bit_cast(u32x4_t, ov);
                     }
+                    *reinterpret_cast<u32x4_t*>(out.p + v * out.cs + out.c0 + 16 * n + 8 * half) = o;
                 }
             }
         }
