@@ -387,6 +387,8 @@ __global__ __launch_bounds__(64 * CONV_WAVES) void conv3_mfma_c1(const float* __
     const int x0 = (int)(wt - (int64_t)row * tiles_x) * 16 * CONV_MT;
     const int t = row / H, y = row - t * H;
     const int i = lane & 15, g = lane >> 4;
+    // outputs staged per wave as [tile][voxel][16 channels] for 16-byte stores
+    __shared__ __bf16 obuf[CONV_WAVES][CONV_MT * NB][16 * 16];
     bf16x8 b[NB];
 #pragma unroll
     for (int n = 0; n < NB; ++n) b[n] = frag[n * 64 + lane];
@@ -409,17 +411,27 @@ __global__ __launch_bounds__(64 * CONV_WAVES) void conv3_mfma_c1(const float* __
         for (int n = 0; n < NB; ++n)
             acc[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[n], f32x4{0.f, 0.f, 0.f, 0.f},
                                                              0, 0, 0);
-        const int64_t obase = ((int64_t)t * H + y) * W;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int xo = x0 + 16 * m + 4 * g + r;
-            if (xo >= W) continue;
+        for (int n = 0; n < NB; ++n) {
+            const float bco = bias[16 * n + i];
 #pragma unroll
-            for (int n = 0; n < NB; ++n) {
-                const int co = 16 * n + i;
-                out.p[(obase + xo) * out.cs + out.c0 + co] = (__bf16)fmaxf(acc[n][r] + bias[co], 0.f);
-            }
+            for (int r = 0; r < 4; ++r)
+                obuf[wave][m * NB + n][(4 * g + r) * 16 + i] = (__bf16)fmaxf(acc[n][r] + bco, 0.f);
         }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int64_t obase = ((int64_t)t * H + y) * W;
+#pragma unroll
+    for (int c0 = 0; c0 < CONV_MT * NB * 32; c0 += 64) {
+        const int c = c0 + lane;
+        const int tl = c >> 5, vv = (c & 31) >> 1, half = c & 1;
+        const int m = tl / NB, n = tl - m * NB;
+        const int xo = x0 + 16 * m + vv;
+        if (xo < W)
+            *reinterpret_cast<u32x4_t*>(out.p + (obase + xo) * out.cs + out.c0 + 16 * n + 8 * half) =
+                *reinterpret_cast<const u32x4_t*>(&obuf[wave][tl][vv * 16 + 8 * half]);
     }
 }
 
