@@ -111,16 +111,24 @@ int conv_runs(int64_t tiles, int T) {
     return (int)(r < 1 ? 1 : r);
 }
 
-hipError_t conv_fwd(int cin, int cout, View in, View out, const bf16x8* frag, const float* bias,
-                    View mask, int mode, hipStream_t s) {
+// up.p set: input channels [0, cup) are the 2x upsampling of `up` (see
+// conv3_stream); otherwise `in` holds every input channel.
+hipError_t conv_fwd_up(int cin, int cout, View in, View up, int cup, View out,
+                       const bf16x8* frag, const float* bias, View mask, int mode,
+                       hipStream_t s) {
     using namespace sfseg::unet;
 #define SFSEG_CONV_CASE(CI, CO)                                                                   \
     if (cin == CI && cout == CO) {                                                                \
         constexpr int RB = conv_rows(CI), XB = conv_xb(CI);                                       \
         const int64_t tiles = (int64_t)((out.H + RB - 1) / RB) * ((out.W + XB - 1) / XB);         \
         const int runs = conv_runs(tiles, out.T);                                                 \
-        hipLaunchKernelGGL((conv3_stream<CI, CO, RB, XB>), dim3((unsigned)(tiles * runs)),        \
-                           dim3(256), 0, s, in, out, frag, bias, mask, mode, runs);               \
+        if (up.p)                                                                                 \
+            hipLaunchKernelGGL((conv3_stream<CI, CO, RB, XB, true>), dim3((unsigned)(tiles * runs)), \
+                               dim3(256), 0, s, in, up, cup, out, frag, bias, mask, mode, runs);  \
+        else                                                                                      \
+            hipLaunchKernelGGL((conv3_stream<CI, CO, RB, XB, false>),                             \
+                               dim3((unsigned)(tiles * runs)), dim3(256), 0, s, in, up, cup, out, \
+                               frag, bias, mask, mode, runs);                                     \
         return hipGetLastError();                                                                 \
     }
     SFSEG_CONV_CASE(16, 16)
@@ -136,6 +144,12 @@ hipError_t conv_fwd(int cin, int cout, View in, View out, const bf16x8* frag, co
     SFSEG_CONV_CASE(16, 48)
 #undef SFSEG_CONV_CASE
     return hipErrorInvalidValue;
+}
+
+hipError_t conv_fwd(int cin, int cout, View in, View out, const bf16x8* frag, const float* bias,
+                    View mask, int mode, hipStream_t s) {
+    const View none{nullptr, 0, 0, 0, 0, 0};
+    return conv_fwd_up(cin, cout, in, none, 0, out, frag, bias, mask, mode, s);
 }
 
 hipError_t conv_wgrad(int cin, int cout, View gz, View in, const float* in32, float* part,
@@ -392,9 +406,17 @@ int sfseg_unet_forward(sfseg_unet* n, const float* S, int32_t T, int32_t H, int3
     HIP_TRY(hipGetLastError());
     HIP_TRY(conv_fwd(96, 32, cat2, d2a, n->ffwd[DEC2A], bias(DEC2A), none, 0, s));
     HIP_TRY(conv_fwd(32, 32, d2a, d2, n->ffwd[DEC2B], bias(DEC2B), none, 0, s));
-    hipLaunchKernelGGL(sfseg::unet::up2_fwd, dim3(grid_for(nv * 4)), dim3(256), 0, s, d2, u1, 32);
-    HIP_TRY(hipGetLastError());
-    HIP_TRY(conv_fwd(48, 16, cat1, d1a, n->ffwd[DEC1A], bias(DEC1A), none, 0, s));
+    // The full-resolution upsampled half of the last concatenation is written
+    // out only when the backward pass needs it; otherwise the convolution
+    // reads it at the parent voxels while staging its input.  (At half
+    // resolution the separate upsampling is the cheaper of the two.)
+    if (n->training) {
+        hipLaunchKernelGGL(sfseg::unet::up2_fwd, dim3(grid_for(nv * 4)), dim3(256), 0, s, d2, u1, 32);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(conv_fwd(48, 16, cat1, d1a, n->ffwd[DEC1A], bias(DEC1A), none, 0, s));
+    } else {
+        HIP_TRY(conv_fwd_up(48, 16, cat1, d2, 32, d1a, n->ffwd[DEC1A], bias(DEC1A), none, 0, s));
+    }
     HIP_TRY(conv_fwd(16, 16, d1a, d1, n->ffwd[DEC1B], bias(DEC1B), none, 0, s));
     hipLaunchKernelGGL(sfseg::unet::head_fwd, dim3(grid_for(nv)), dim3(256), 0, s, d1,
                        w + layer_offset(HEAD), n->z, n->xh);

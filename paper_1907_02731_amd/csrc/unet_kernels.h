@@ -186,8 +186,14 @@ struct ConvLds {
     static_assert(MT >= 1 && TPR % MT == 0, "a wave's tiles lie in one row");
 };
 
-template <int CIN, int COUT, int RB, int XB>
-__global__ __launch_bounds__(256) void conv3_stream(View in, View out,
+//
+// With UP, input channels [0, cup) are the nearest-neighbour 2x upsampling
+// of `up` (half resolution), read at the parent voxel while the slab is
+// staged, and channels [cup, CIN) come from `in`: the upsampled part of a
+// concatenation is never written out (inference only; training keeps the
+// concatenated tensor for the backward pass).
+template <int CIN, int COUT, int RB, int XB, bool UP>
+__global__ __launch_bounds__(256) void conv3_stream(View in, View up, int cup, View out,
                                                      const bf16x8* __restrict__ frag,
                                                      const float* __restrict__ bias, View mask,
                                                      int mode, int runs) {
@@ -215,26 +221,37 @@ __global__ __launch_bounds__(256) void conv3_stream(View in, View out,
     const u32x4_t zero = {0u, 0u, 0u, 0u};
 
     // This thread's units of a frame slab, unit u = (r * NCG + cg) * VOX + v:
-    // their element offsets inside an input frame (-1 outside the picture).
+    // their element offsets inside an input frame of `in` or, for upsampled
+    // channels, of `up` (-1 outside the picture).
     int64_t uoff[PER];
+    bool fromup[PER];
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
         const int u = j * 256 + threadIdx.x;
         const int v = u % VOX, rest = u / VOX;
         const int cg = rest % NCG, r = rest / NCG;
         const int ys = y0 + r - 1, xs = x0 + v - 1;
-        uoff[j] = (u < UNITS && ys >= 0 && ys < H && xs >= 0 && xs < W)
-                      ? ((int64_t)ys * W + xs) * in.cs + in.c0 + 8 * cg
-                      : -1;
+        const bool ok = u < UNITS && ys >= 0 && ys < H && xs >= 0 && xs < W;
+        fromup[j] = UP && 8 * cg < cup;
+        uoff[j] = !ok ? -1
+                      : fromup[j] ? ((int64_t)(ys >> 1) * up.W + (xs >> 1)) * up.cs + up.c0 + 8 * cg
+                                  : ((int64_t)ys * W + xs) * in.cs + in.c0 + 8 * cg;
     }
     const int64_t fstride = (int64_t)H * W * in.cs;
+    const int64_t ustride = (int64_t)up.H * up.W * up.cs;
     auto load_frame = [&](int ts, u32x4_t* reg) {
         const bool tin = ts >= 0 && ts < T;
         const __bf16* fb = in.p + (tin ? (int64_t)ts * fstride : 0);
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
             u32x4_t val = zero;
-            if (tin && uoff[j] >= 0) val = *reinterpret_cast<const u32x4_t*>(fb + uoff[j]);
+            if constexpr (UP) {
+                const __bf16* ub = up.p + (tin ? (int64_t)(ts >> 1) * ustride : 0);
+                if (tin && uoff[j] >= 0)
+                    val = *reinterpret_cast<const u32x4_t*>((fromup[j] ? ub : fb) + uoff[j]);
+            } else {
+                if (tin && uoff[j] >= 0) val = *reinterpret_cast<const u32x4_t*>(fb + uoff[j]);
+            }
             reg[j] = val;
         }
     };
@@ -646,19 +663,30 @@ __global__ void pool2_bwd(View gout, View skip, View act, View gin, int C) {
 }
 
 // out[v] = in[parent(v)] (nearest 2x, cropped to out's size).
-__global__ void up2_fwd(View in, View out, int C) {
-    // one thread per (output voxel, 8 channels): 16-byte loads and stores
-    const int C8 = C / 8;
-    const int64_t n = (int64_t)out.T * out.H * out.W * C8;
-    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n;
-         idx += (int64_t)gridDim.x * blockDim.x) {
-        const int c = 8 * (int)(idx % C8);
-        const int64_t v = idx / C8;
-        const int x = (int)(v % out.W), y = (int)((v / out.W) % out.H), t = (int)(v / ((int64_t)out.W * out.H));
+template <typename I>
+__device__ __forceinline__ void up2_body(const View& in, const View& out, int C8, I n) {
+    for (I idx = (I)blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += (I)gridDim.x * blockDim.x) {
+        const int c = 8 * (int)(idx % (I)C8);
+        const I v = idx / (I)C8;
+        const I hw = (I)out.H * (I)out.W;
+        const int t = (int)(v / hw);
+        const I rem = v - (I)t * hw;
+        const int y = (int)(rem / (I)out.W), x = (int)(rem - (I)y * (I)out.W);
         const int64_t pv = ((int64_t)(t >> 1) * in.H + (y >> 1)) * in.W + (x >> 1);
-        *reinterpret_cast<u32x4_t*>(out.p + v * out.cs + out.c0 + c) =
+        *reinterpret_cast<u32x4_t*>(out.p + (int64_t)v * out.cs + out.c0 + c) =
             *reinterpret_cast<const u32x4_t*>(in.p + pv * in.cs + in.c0 + c);
     }
+}
+
+__global__ void up2_fwd(View in, View out, int C) {
+    // one thread per (output voxel, 8 channels): 16-byte loads and stores;
+    // index arithmetic in 32 bits where the index range allows
+    const int C8 = C / 8;
+    const int64_t n = (int64_t)out.T * out.H * out.W * C8;
+    if (n < ((int64_t)1 << 32))
+        up2_body<uint32_t>(in, out, C8, (uint32_t)n);
+    else
+        up2_body<uint64_t>(in, out, C8, (uint64_t)n);
 }
 
 // g_in[p] = sum of g_out over p's children inside g_out, zero where act[p] <= 0.
