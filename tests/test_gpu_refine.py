@@ -81,6 +81,26 @@ def test_refinement_matches_the_oracle(case):
     assert mu >= float(xk @ y) / float(xk @ xk) * (1 - 1e-6)
 
 
+@pytest.mark.parametrize("plan", [(1, 1), (2, 1), (3, 1)])
+def test_refinement_on_every_plan_shape(plan):
+    """The products go through the context's step kernel in its one-
+    application mode: the 512-thread shape, the matrix-core shape and the
+    two-step shape give the same refinement to float32 rounding."""
+    shape, cfg = CASES[2]
+    S = _clip(shape, 50)
+    with Solver(_t(S), **_kw(cfg)) as sol:
+        sol.set_plan(*plan)
+        sol.iterate(max_iters=2, tol=0.0)
+        xk = sol.eigvec().cpu().numpy().astype(np.float64).ravel()
+        xg, mu = sol.refine_frames()
+        xg = xg.cpu().numpy().astype(np.float64).ravel()
+    ref = frame_ritz(MatrixFree(S, None, cfg).apply, xk, S.shape)
+    xr = ref["x"] / np.linalg.norm(ref["x"])
+    err = float(np.linalg.norm(xg - xr))
+    print(f"\nplan {plan}: |x_gpu - x_oracle| = {err:.2e}", flush=True)
+    assert err <= 1e-5 and abs(mu - ref["mu"]) <= 1e-6 * ref["mu"]
+
+
 def test_refinement_bf16_storage_within_budget():
     shape, cfg = CASES[2]
     S = _clip(shape, 7)
