@@ -579,8 +579,8 @@ def bench_segment(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU sharding is described in the design notes, not built.",
+        print(f"bench.py: the library and this benchmark run on one GPU (asked for --gpus "
+              f"{args.gpus}); sharding a clip or a batch across GPUs is not implemented.",
               file=sys.stderr)
         sys.exit(2)
     if args.workload == "batch":
