@@ -2,7 +2,8 @@
 
     python -m paper_1907_02731_amd.train_warmstart [--n 2000] [--epochs 4] [--out PATH]
 
-1. draws ``n`` seeded synthetic clips of 32 x 128 x 224 (seeds 40000 + i),
+1. draws ``n`` seeded synthetic clips of 32 x 128 x 224 (``--shape``; seeds
+   40000 + i),
 2. computes each clip's principal eigenvector with the plain method (batched
    power iteration to delta < 1e-6) as the training target,
 3. trains the network with Adam on 1 - cos(x^, x*) or, with --loss spectral,
@@ -69,19 +70,22 @@ def main(argv=None):
                     help="cos: 1 - cos(x^, x*); spectral: 1 - cos(M^k x^, x*)")
     ap.add_argument("--k", type=int, default=32, help="power steps inside the spectral loss")
     ap.add_argument("--init", default="", help="start from these parameters (.npy)")
+    ap.add_argument("--shape", default=",".join(str(v) for v in TRAIN_SHAPE),
+                    help="training clip shape T,H,W")
     args = ap.parse_args(argv)
 
+    shape = tuple(int(v) for v in args.shape.split(","))
     t0 = time.time()
     clips = []
     for i in range(0, args.n, 100):
-        clips += training_clips(min(100, args.n - i), seed0=40000 + i)
+        clips += training_clips(min(100, args.n - i), seed0=40000 + i, shape=shape)
         log(f"clips {len(clips)}/{args.n} ({time.time() - t0:.0f}s)")
     targets = eigenvector_targets(clips, tol=1e-6, log=log)
     inputs = [torch.from_numpy(c).cuda() for c in clips]
     del clips
     log(f"data ready ({time.time() - t0:.0f}s)")
 
-    with UNet(TRAIN_SHAPE, training=True) as net:
+    with UNet(shape, training=True) as net:
         net.set_params(load_params(args.init) if args.init else he_init(args.seed))
         if args.loss == "cos":
             losses = train(net, inputs, targets, epochs=args.epochs, lr=args.lr,
