@@ -200,3 +200,37 @@ def test_batch_at_real_resolutions_matches_the_oracle():
         assert r.iters == K
         assert np.linalg.norm(x - ref["x"]) <= 1e-5
         assert abs(r.lam - ref["lam"]) <= 1e-6 * ref["lam"]
+
+
+def test_batched_warm_start_reaches_the_same_eigenvectors():
+    """The batched form started from the warm-start network's estimates (the
+    shipped weights) on ragged clips of the benchmark's kind: per clip the
+    same Rayleigh quotient as the plain method from S (to 1e-6), and the two
+    vectors within the error that stopping at delta leaves, delta r / (1 - r)
+    for each, r the contraction over the plain run's last 20 steps, with a
+    factor 3 for steps before the asymptotic rate."""
+    from paper_1907_02731_amd.synth import full_clip
+    from paper_1907_02731_amd.warmstart import GRAPH, WEIGHTS, UNet, load_params
+    shapes = [(24, 96, 160), (40, 120, 214), (33, 80, 150)]
+    clips = [torch.from_numpy(full_clip(5000 + i, T=T, H=H, W=W)).to(DEV)
+             for i, (T, H, W) in enumerate(shapes)]
+    tol = 1e-5
+    with UNet(tuple(max(s[d] for s in shapes) for d in range(3))) as net:
+        net.set_params(load_params(WEIGHTS))
+        x0s = [net.forward(S) for S in clips]
+    with BatchSolver(clips, **GRAPH) as bs:
+        rw = bs.iterate(x0s, max_iters=20000, tol=tol)
+        xw = [x.cpu().numpy().astype(np.float64).ravel() for x in bs.eigvecs()]
+    for i, S in enumerate(clips):
+        with Solver(S, **GRAPH) as sol:
+            rc = sol.iterate(max_iters=20000, tol=tol)
+            xc = sol.eigvec().cpu().numpy().astype(np.float64).ravel()
+            r20 = sol.iterate(max_iters=rc.iters - 20, tol=0.0)
+        rate = (rc.delta / r20.delta) ** (1.0 / 20)
+        bound = 3.0 * (rc.delta + rw[i].delta) * rate / (1.0 - rate)
+        d = float(np.linalg.norm(xw[i] - xc))
+        print(f"\nclip {shapes[i]}: plain {rc.iters} steps, batched warm {rw[i].iters}; "
+              f"contraction {rate:.5f}, |x_w - x_c| {d:.2e} <= {bound:.2e}", flush=True)
+        assert rc.converged and rw[i].converged
+        assert abs(rw[i].lam - rc.lam) <= 1e-6 * rc.lam
+        assert 0.0 < rate < 1.0 and d <= bound
