@@ -58,7 +58,8 @@ def evaluate(net: UNet, seeds, tol: float = 1e-5):
 
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
-    ap.add_argument("--n", type=int, default=2000)
+    ap.add_argument("--n", default="2000",
+                    help="training clips (one count, or one per --shape entry)")
     ap.add_argument("--epochs", type=int, default=4)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--lr-final", type=float, default=5e-5)
@@ -71,21 +72,29 @@ def main(argv=None):
     ap.add_argument("--k", type=int, default=32, help="power steps inside the spectral loss")
     ap.add_argument("--init", default="", help="start from these parameters (.npy)")
     ap.add_argument("--shape", default=",".join(str(v) for v in TRAIN_SHAPE),
-                    help="training clip shape T,H,W")
+                    help="training clip shape T,H,W (several: T,H,W;T,H,W)")
     args = ap.parse_args(argv)
 
-    shape = tuple(int(v) for v in args.shape.split(","))
+    shapes = [tuple(int(v) for v in sh.split(",")) for sh in args.shape.split(";")]
+    counts = [int(v) for v in args.n.split(",")]
+    if len(counts) == 1:
+        counts = counts * len(shapes)
+    if len(counts) != len(shapes):
+        ap.error("--n needs one count or one per shape")
     t0 = time.time()
     clips = []
-    for i in range(0, args.n, 100):
-        clips += training_clips(min(100, args.n - i), seed0=40000 + i, shape=shape)
-        log(f"clips {len(clips)}/{args.n} ({time.time() - t0:.0f}s)")
+    seed = 40000
+    for shape, n in zip(shapes, counts):
+        for i in range(0, n, 100):
+            clips += training_clips(min(100, n - i), seed0=seed + i, shape=shape)
+            log(f"clips {len(clips)}/{sum(counts)} ({time.time() - t0:.0f}s)")
+        seed += n
     targets = eigenvector_targets(clips, tol=1e-6, log=log)
     inputs = [torch.from_numpy(c).cuda() for c in clips]
     del clips
     log(f"data ready ({time.time() - t0:.0f}s)")
 
-    with UNet(shape, training=True) as net:
+    with UNet(tuple(max(sh[d] for sh in shapes) for d in range(3)), training=True) as net:
         net.set_params(load_params(args.init) if args.init else he_init(args.seed))
         if args.loss == "cos":
             losses = train(net, inputs, targets, epochs=args.epochs, lr=args.lr,

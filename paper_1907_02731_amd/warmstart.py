@@ -221,22 +221,30 @@ def train_spectral(net: UNet, inputs: Sequence[torch.Tensor], targets: Sequence[
     losses: List[float] = []
     step = 0
     t0 = time.time()
-    g_buf = None
-    with Solver(inputs[0], **graph) as sol:
+    sols: Dict[Tuple[int, ...], Solver] = {}   # one context per clip shape
+    g_bufs: Dict[Tuple[int, ...], torch.Tensor] = {}
+    try:
         for _ in range(epochs):
             for i in rng.permutation(len(inputs)):
                 step += 1
                 rate = lr_final + 0.5 * (lr - lr_final) * (1 + math.cos(math.pi * (step - 1) / total))
+                shape = tuple(int(v) for v in inputs[i].shape)
+                if shape not in sols:
+                    sols[shape] = Solver(inputs[i], **graph)
+                sol = sols[shape]
                 sol.set_features(inputs[i])
                 xhat = net.forward(inputs[i])
-                g, loss = sol.spectral_grad(xhat, targets[i], k, out=g_buf)
-                g_buf = g
+                g, loss = sol.spectral_grad(xhat, targets[i], k, out=g_bufs.get(shape))
+                g_bufs[shape] = g
                 net.backward_from(g)
                 net.adam_step(rate, step)
                 losses.append(loss)
                 if log and (step % log_every == 0 or step == total):
                     log(f"step {step}/{total} loss after {k} steps (mean of last {log_every}) "
                         f"{np.mean(losses[-log_every:]):.6f} rate {rate:.2e} {time.time() - t0:.1f}s")
+    finally:
+        for sol in sols.values():
+            sol.close()
     return losses
 
 
