@@ -389,7 +389,12 @@ typedef struct sfseg_unet sfseg_unet;
 int64_t sfseg_unet_param_count(void);
 
 /* Create a network (weights zero until sfseg_unet_set_params).  training != 0
- * also allocates gradient buffers.  SFSEG_ERR_INVALID_ARG for sizes < 1 or
+ * also allocates gradient buffers and the activations that the backward pass
+ * reads; an inference network (training = 0) reads S in its first layer,
+ * forms the upsampled half of the last skip concatenation while its
+ * convolution stages its input, and runs the head in the last convolution,
+ * so it holds neither (same output bit for bit, 108 bytes per voxel less
+ * memory).  SFSEG_ERR_INVALID_ARG for sizes < 1 or
  * max_T * max_H * max_W * 48 >= 2^31; SFSEG_ERR_OOM / SFSEG_ERR_HIP. */
 int sfseg_unet_create(int32_t max_T, int32_t max_H, int32_t max_W, int32_t training, void *stream,
                       sfseg_unet **out);
@@ -400,9 +405,9 @@ int sfseg_unet_set_params(sfseg_unet *net, const float *host_params, int64_t cou
 int sfseg_unet_get_params(const sfseg_unet *net, float *host_params, int64_t count);
 
 /* x^ = net(S) for a T x H x W volume (device float32 in and out, caller
- * owned, contiguous).  Stream-ordered; S is copied, so it may be reused once
- * the stream reaches this call.  SFSEG_ERR_INVALID_ARG for sizes outside
- * 1..max. */
+ * owned, contiguous).  Stream-ordered: S is read by the call's first kernel
+ * (copied first in a training network), `out` written by its last, so they
+ * may be the same buffer.  SFSEG_ERR_INVALID_ARG for sizes outside 1..max. */
 int sfseg_unet_forward(sfseg_unet *net, const float *S, int32_t T, int32_t H, int32_t W,
                        float *out);
 

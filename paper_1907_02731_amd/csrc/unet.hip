@@ -103,6 +103,9 @@ int grid_for(int64_t n, int per = 256) {
 // 17 KB for 64 and 26 KB for 96.  Frame runs per tile: enough blocks to give every
 // CU several.
 constexpr int conv_rows(int cin) { return cin <= 32 ? 4 : 2; }
+// Split K over the four waves (see conv3_stream) where the weight fragments
+// would otherwise be read by every wave for one tile each: the 96 -> 32 layer.
+constexpr int conv_ks(int cin, int cout) { return cin == 96 && cout == 32 ? 4 : 1; }
 constexpr int conv_xb(int) { return 32; }
 int conv_runs(int64_t tiles, int T) {
     const int64_t want = 2048;
@@ -111,7 +114,8 @@ int conv_runs(int64_t tiles, int T) {
     return (int)(r < 1 ? 1 : r);
 }
 
-// up.p set: input channels [0, cup) are the 2x upsampling of `up` (see
+// up.p set: input channels [0, cup) are the 2x upsampling of `up` and
+// channels [cup, cin) are the first cin - cup channels of `in` (see
 // conv3_stream); otherwise `in` holds every input channel.
 hipError_t conv_fwd_up(int cin, int cout, View in, View up, int cup, View out,
                        const bf16x8* frag, const float* bias, View mask, int mode,
@@ -119,16 +123,17 @@ hipError_t conv_fwd_up(int cin, int cout, View in, View up, int cup, View out,
     using namespace sfseg::unet;
 #define SFSEG_CONV_CASE(CI, CO)                                                                   \
     if (cin == CI && cout == CO) {                                                                \
-        constexpr int RB = conv_rows(CI), XB = conv_xb(CI);                                       \
+        constexpr int RB = conv_rows(CI), XB = conv_xb(CI), KS = conv_ks(CI, CO);                 \
         const int64_t tiles = (int64_t)((out.H + RB - 1) / RB) * ((out.W + XB - 1) / XB);         \
         const int runs = conv_runs(tiles, out.T);                                                 \
         if (up.p)                                                                                 \
             hipLaunchKernelGGL((conv3_stream<CI, CO, RB, XB, true>), dim3((unsigned)(tiles * runs)), \
-                               dim3(256), 0, s, in, up, cup, out, frag, bias, mask, mode, runs);  \
+                               dim3(256), 0, s, in, up, cup, out, frag, bias, mask, mode, runs,   \
+                               nullptr, nullptr);                                                 \
         else                                                                                      \
-            hipLaunchKernelGGL((conv3_stream<CI, CO, RB, XB, false>),                             \
+            hipLaunchKernelGGL((conv3_stream<CI, CO, RB, XB, false, false, KS>),                  \
                                dim3((unsigned)(tiles * runs)), dim3(256), 0, s, in, up, cup, out, \
-                               frag, bias, mask, mode, runs);                                     \
+                               frag, bias, mask, mode, runs, nullptr, nullptr);                   \
         return hipGetLastError();                                                                 \
     }
     SFSEG_CONV_CASE(16, 16)
@@ -150,6 +155,32 @@ hipError_t conv_fwd(int cin, int cout, View in, View out, const bf16x8* frag, co
                     View mask, int mode, hipStream_t s) {
     const View none{nullptr, 0, 0, 0, 0, 0};
     return conv_fwd_up(cin, cout, in, none, 0, out, frag, bias, mask, mode, s);
+}
+
+// The last 16 -> 16 convolution with the 1x1x1 head fused (inference): the
+// network's output xh (FP32, T x H x W of `dims`) is written, the
+// convolution's activations are not.
+hipError_t conv_fwd_head(View in, View dims, const bf16x8* frag, const float* bias,
+                         const float* head_w, float* xh, hipStream_t s) {
+    using namespace sfseg::unet;
+    constexpr int RB = conv_rows(16), XB = conv_xb(16);
+    const View none{nullptr, 0, 0, 0, 0, 0};
+    const int64_t tiles = (int64_t)((dims.H + RB - 1) / RB) * ((dims.W + XB - 1) / XB);
+    const int runs = conv_runs(tiles, dims.T);
+    hipLaunchKernelGGL((conv3_stream<16, 16, RB, XB, false, true>), dim3((unsigned)(tiles * runs)),
+                       dim3(256), 0, s, in, none, 0, dims, frag, bias, none, 0, runs, head_w, xh);
+    return hipGetLastError();
+}
+
+// The first layer (one FP32 input channel).
+hipError_t conv_fwd_c1(const float* in, View out, const bf16x8* frag, const float* bias,
+                       hipStream_t s) {
+    using namespace sfseg::unet;
+    const int64_t tiles = (int64_t)((out.H + C1_RB - 1) / C1_RB) * ((out.W + C1_XB - 1) / C1_XB);
+    const int runs = conv_runs(tiles, out.T);
+    hipLaunchKernelGGL(conv3_c1_stream<16>, dim3((unsigned)(tiles * runs)), dim3(256), 0, s, in,
+                       out, frag, bias, runs);
+    return hipGetLastError();
 }
 
 hipError_t conv_wgrad(int cin, int cout, View gz, View in, const float* in32, float* part,
@@ -271,16 +302,22 @@ int sfseg_unet_create(int32_t max_T, int32_t max_H, int32_t max_W, int32_t train
             if (!rc && l != ENC1A) rc = dalloc(n, &n->fbwd[l], frag_elems(kLayers[l].cout, kLayers[l].cin));
         }
         if (rc) break;
-        if ((rc = dalloc(n, &n->in32, nfull)) || (rc = dalloc(n, &n->z, nfull)) ||
-            (rc = dalloc(n, &n->xh, nfull)) || (rc = dalloc(n, &n->e1a, nfull * 16)) ||
-            (rc = dalloc(n, &n->cat1, nfull * 48)) || (rc = dalloc(n, &n->p1, nh * 16)) ||
-            (rc = dalloc(n, &n->e2a, nh * 32)) || (rc = dalloc(n, &n->cat2, nh * 96)) ||
-            (rc = dalloc(n, &n->p2, nq * 32)) || (rc = dalloc(n, &n->ba, nq * 64)) ||
-            (rc = dalloc(n, &n->bb, nq * 64)) || (rc = dalloc(n, &n->d2a, nh * 32)) ||
-            (rc = dalloc(n, &n->d2, nh * 32)) || (rc = dalloc(n, &n->d1a, nfull * 16)) ||
-            (rc = dalloc(n, &n->d1, nfull * 16)))
+        // Inference keeps only what the forward pass reads: the first layer
+        // reads S itself, the full-resolution skip tensor has its 16 channels
+        // alone (the upsampled half of the concatenation is never formed) and
+        // the head is fused into the last convolution.
+        const int64_t cat1_ch = n->training ? 48 : 16;
+        if ((rc = dalloc(n, &n->e1a, nfull * 16)) || (rc = dalloc(n, &n->cat1, nfull * cat1_ch)) ||
+            (rc = dalloc(n, &n->p1, nh * 16)) || (rc = dalloc(n, &n->e2a, nh * 32)) ||
+            (rc = dalloc(n, &n->cat2, nh * 96)) || (rc = dalloc(n, &n->p2, nq * 32)) ||
+            (rc = dalloc(n, &n->ba, nq * 64)) || (rc = dalloc(n, &n->bb, nq * 64)) ||
+            (rc = dalloc(n, &n->d2a, nh * 32)) || (rc = dalloc(n, &n->d2, nh * 32)) ||
+            (rc = dalloc(n, &n->d1a, nfull * 16)))
             break;
         if (n->training) {
+            if ((rc = dalloc(n, &n->in32, nfull)) || (rc = dalloc(n, &n->z, nfull)) ||
+                (rc = dalloc(n, &n->xh, nfull)) || (rc = dalloc(n, &n->d1, nfull * 16)))
+                break;
             if ((rc = dalloc(n, &n->gA, nfull * 16)) || (rc = dalloc(n, &n->gB, nfull * 16)) ||
                 (rc = dalloc(n, &n->gC, nfull * 48)) || (rc = dalloc(n, &n->gD, nh * 32)) ||
                 (rc = dalloc(n, &n->gE, nh * 32)) || (rc = dalloc(n, &n->gF, nh * 96)) ||
@@ -369,9 +406,13 @@ int sfseg_unet_forward(sfseg_unet* n, const float* S, int32_t T, int32_t H, int3
     const int64_t nv = (int64_t)T * H * W;
     const int Th = (int)ceil2(T), Hh = (int)ceil2(H), Wh = (int)ceil2(W);
     const int Tq = (int)ceil2(Th), Hq = (int)ceil2(Hh), Wq = (int)ceil2(Wh);
-    HIP_TRY(hipMemcpyAsync(n->in32, S, sizeof(float) * nv, hipMemcpyDeviceToDevice, s));
+    const bool tr = n->training != 0;
+    if (tr) HIP_TRY(hipMemcpyAsync(n->in32, S, sizeof(float) * nv, hipMemcpyDeviceToDevice, s));
     const View none{nullptr, 0, 0, 0, 0, 0};
-    const View e1a = view(n->e1a, T, H, W, 16, 0), e1 = view(n->cat1, T, H, W, 48, 32),
+    // e1: channels 32..47 of the concatenation in training, its own
+    // 16-channel tensor in inference
+    const View e1a = view(n->e1a, T, H, W, 16, 0),
+               e1 = tr ? view(n->cat1, T, H, W, 48, 32) : view(n->cat1, T, H, W, 16, 0),
                cat1 = view(n->cat1, T, H, W, 48, 0), u1 = view(n->cat1, T, H, W, 48, 0),
                p1 = view(n->p1, Th, Hh, Wh, 16, 0), e2a = view(n->e2a, Th, Hh, Wh, 32, 0),
                e2 = view(n->cat2, Th, Hh, Wh, 96, 64), cat2 = view(n->cat2, Th, Hh, Wh, 96, 0),
@@ -381,15 +422,7 @@ int sfseg_unet_forward(sfseg_unet* n, const float* S, int32_t T, int32_t H, int3
                d1a = view(n->d1a, T, H, W, 16, 0), d1 = view(n->d1, T, H, W, 16, 0);
     const float* w = n->w;
     auto bias = [&](int l) { return w + layer_offset(l) + layer_weights(l); };
-    {
-        const int tiles_x = (W + 16 * sfseg::unet::CONV_MT - 1) / (16 * sfseg::unet::CONV_MT);
-        const int64_t waves = (int64_t)T * H * tiles_x;
-        hipLaunchKernelGGL(sfseg::unet::conv3_mfma_c1<16>,
-                           dim3((unsigned)((waves + sfseg::unet::CONV_WAVES - 1) / sfseg::unet::CONV_WAVES)),
-                           dim3(64 * sfseg::unet::CONV_WAVES), 0, s, n->in32, e1a, n->ffwd[ENC1A],
-                           bias(ENC1A));
-        HIP_TRY(hipGetLastError());
-    }
+    HIP_TRY(conv_fwd_c1(tr ? n->in32 : S, e1a, n->ffwd[ENC1A], bias(ENC1A), s));
     HIP_TRY(conv_fwd(16, 16, e1a, e1, n->ffwd[ENC1B], bias(ENC1B), none, 0, s));
     hipLaunchKernelGGL(sfseg::unet::pool2_fwd, dim3(grid_for((int64_t)Th * Hh * Wh * 2)), dim3(256), 0,
                        s, e1, p1, 16);
@@ -406,22 +439,24 @@ int sfseg_unet_forward(sfseg_unet* n, const float* S, int32_t T, int32_t H, int3
     HIP_TRY(hipGetLastError());
     HIP_TRY(conv_fwd(96, 32, cat2, d2a, n->ffwd[DEC2A], bias(DEC2A), none, 0, s));
     HIP_TRY(conv_fwd(32, 32, d2a, d2, n->ffwd[DEC2B], bias(DEC2B), none, 0, s));
-    // The full-resolution upsampled half of the last concatenation is written
-    // out only when the backward pass needs it; otherwise the convolution
-    // reads it at the parent voxels while staging its input.  (At half
-    // resolution the separate upsampling is the cheaper of the two.)
-    if (n->training) {
+    if (tr) {
+        // the backward pass reads the concatenation, d1 and z
         hipLaunchKernelGGL(sfseg::unet::up2_fwd, dim3(grid_for(nv * 4)), dim3(256), 0, s, d2, u1, 32);
         HIP_TRY(hipGetLastError());
         HIP_TRY(conv_fwd(48, 16, cat1, d1a, n->ffwd[DEC1A], bias(DEC1A), none, 0, s));
+        HIP_TRY(conv_fwd(16, 16, d1a, d1, n->ffwd[DEC1B], bias(DEC1B), none, 0, s));
+        hipLaunchKernelGGL(sfseg::unet::head_fwd, dim3(grid_for(nv)), dim3(256), 0, s, d1,
+                           w + layer_offset(HEAD), n->z, n->xh);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(out, n->xh, sizeof(float) * nv, hipMemcpyDeviceToDevice, s));
     } else {
-        HIP_TRY(conv_fwd_up(48, 16, cat1, d2, 32, d1a, n->ffwd[DEC1A], bias(DEC1A), none, 0, s));
+        // the upsampled half of the concatenation is read at the parent voxels
+        // while the convolution stages its input (at half resolution the
+        // separate upsampling is the cheaper of the two), and the head runs
+        // in the last convolution's epilogue
+        HIP_TRY(conv_fwd_up(48, 16, e1, d2, 32, d1a, n->ffwd[DEC1A], bias(DEC1A), none, 0, s));
+        HIP_TRY(conv_fwd_head(d1a, d1a, n->ffwd[DEC1B], bias(DEC1B), w + layer_offset(HEAD), out, s));
     }
-    HIP_TRY(conv_fwd(16, 16, d1a, d1, n->ffwd[DEC1B], bias(DEC1B), none, 0, s));
-    hipLaunchKernelGGL(sfseg::unet::head_fwd, dim3(grid_for(nv)), dim3(256), 0, s, d1,
-                       w + layer_offset(HEAD), n->z, n->xh);
-    HIP_TRY(hipGetLastError());
-    HIP_TRY(hipMemcpyAsync(out, n->xh, sizeof(float) * nv, hipMemcpyDeviceToDevice, s));
     n->T = T;
     n->H = H;
     n->W = W;

@@ -59,84 +59,15 @@ __device__ __forceinline__ bf16x8 zero8() {
 // ---------------------------------------------------------------------------
 // Implicit-GEMM convolution (forward, or backward-data on mirrored fragments)
 // ---------------------------------------------------------------------------
-// A wave computes MT 16-voxel tiles along x of one row (t, y) for all COUT
-// channels.  frag[((q * NB + nb) * 64 + lane)] holds the 8 B-operand values of
-// K chunk q (k = 32 q + 8 (lane / 16) + e) and output block nb (co = 16 nb +
-// lane % 16).  mode 0: + bias, ReLU; mode 1: no bias, multiply by
-// (mask > 0) if mask.p is set.
-constexpr int CONV_MT = 4;
-constexpr int CONV_WAVES = 4;
+// The head's activation.
+__device__ __forceinline__ float softplus(float z) { return z > 20.f ? z : log1pf(expf(z)); }
 
-template <int CIN, int COUT>
-__global__ __launch_bounds__(64 * CONV_WAVES) void conv3_mfma(View in, View out,
-                                                                const bf16x8* __restrict__ frag,
-                                                                const float* __restrict__ bias,
-                                                                View mask, int mode) {
-    constexpr int NB = COUT / 16;
-    constexpr int NQ = (27 * CIN + 31) / 32;
-    static_assert(CIN % 8 == 0 && COUT % 16 == 0, "channel blocking");
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const int T = out.T, H = out.H, W = out.W;
-    const int tiles_x = (W + 16 * CONV_MT - 1) / (16 * CONV_MT);
-    const int64_t wt = (int64_t)blockIdx.x * CONV_WAVES + wave;
-    if (wt >= (int64_t)T * H * tiles_x) return;  // whole wave: no barrier follows
-    const int row = (int)(wt / tiles_x);
-    const int x0 = (int)(wt - (int64_t)row * tiles_x) * 16 * CONV_MT;
-    const int t = row / H, y = row - t * H;
-    const int i = lane & 15, g = lane >> 4;
-
-    f32x4 acc[CONV_MT][NB];
-#pragma unroll
-    for (int m = 0; m < CONV_MT; ++m)
-#pragma unroll
-        for (int n = 0; n < NB; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
-
-    for (int q = 0; q < NQ; ++q) {
-        const int k = 32 * q + 8 * g;
-        const int tap = k / CIN, c = k - tap * CIN;
-        bf16x8 b[NB];
-#pragma unroll
-        for (int n = 0; n < NB; ++n) b[n] = frag[((int64_t)q * NB + n) * 64 + lane];
-        const int dt = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
-        const int ts = t + dt, ys = y + dy;
-        const bool rowok = tap < 27 && ts >= 0 && ts < T && ys >= 0 && ys < H;
-        const int64_t rbase = ((int64_t)ts * H + ys) * W;
-#pragma unroll
-        for (int m = 0; m < CONV_MT; ++m) {
-            const int xs = x0 + 16 * m + i + dx;
-            bf16x8 a = zero8();
-            if (rowok && xs >= 0 && xs < W && x0 + 16 * m + i < W)
-                a = load8(in.p + (rbase + xs) * in.cs + in.c0 + c);
-#pragma unroll
-            for (int n = 0; n < NB; ++n)
-                acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[n], acc[m][n], 0, 0, 0);
-        }
-    }
-    const int64_t obase = ((int64_t)t * H + y) * W;
-#pragma unroll
-    for (int m = 0; m < CONV_MT; ++m) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int xo = x0 + 16 * m + 4 * g + r;
-            if (xo >= W) continue;
-            const int64_t v = obase + xo;
-#pragma unroll
-            for (int n = 0; n < NB; ++n) {
-                const int co = 16 * n + i;
-                float val = acc[m][n][r];
-                if (mode == 0) {
-                    val = fmaxf(val + bias[co], 0.f);
-                } else if (mask.p) {
-                    if (!((float)mask.p[v * mask.cs + mask.c0 + co] > 0.f)) val = 0.f;
-                }
-                out.p[v * out.cs + out.c0 + co] = (__bf16)val;
-            }
-        }
-    }
-}
-
-// The same product with the input staged in LDS and streamed along t.  A
+// frag[((q * NB + nb) * 64 + lane)] holds the 8 B-operand values of K chunk
+// q (k = 32 q + 8 (lane / 16) + e) and output block nb (co = 16 nb + lane %
+// 16).  mode 0: + bias, ReLU; mode 1: no bias, multiply by (mask > 0) if
+// mask.p is set.
+//
+// The product runs with the input staged in LDS and streamed along t.  A
 // block (four waves) owns RB output rows (y0 .. y0 + RB - 1) x XB voxels
 // (x0 .. x0 + XB - 1) x all COUT channels over a run of output frames
 // [ta, tb): NT = RB XB / 16 tiles of 16 voxels per frame, wave w taking the
@@ -189,19 +120,35 @@ struct ConvLds {
 //
 // With UP, input channels [0, cup) are the nearest-neighbour 2x upsampling
 // of `up` (half resolution), read at the parent voxel while the slab is
-// staged, and channels [cup, CIN) come from `in`: the upsampled part of a
-// concatenation is never written out (inference only; training keeps the
-// concatenated tensor for the backward pass).
-template <int CIN, int COUT, int RB, int XB, bool UP>
+// staged, and channels [cup, CIN) are channels 0 .. CIN - cup - 1 of `in`:
+// the upsampled part of a concatenation is never written out (inference
+// only; training keeps the concatenated tensor for the backward pass).
+// With HEAD (COUT = 16, mode 0), the outputs are not stored: the 1x1x1 head
+// of the network reads them, rounded to bfloat16 as a stored activation
+// would be, and head_out[v] = softplus(head_w[16] + sum_c head_w[c] out[v][c])
+// is written instead (the same arithmetic, in the same order, as head_fwd).
+//
+// With KS = 4 (split K), the four waves share the block's NT = RB XB / 16
+// tiles and each takes every fourth K chunk (chunk q to wave q % 4); their
+// partial sums meet in LDS and wave w adds the four, in wave order, for its
+// own MT tiles.  The weight fragments, which do not fit in registers for the
+// wide layers, are then read once per block and frame instead of once per
+// wave and frame.
+template <int CIN, int COUT, int RB, int XB, bool UP, bool HEAD = false, int KS = 1>
 __global__ __launch_bounds__(256) void conv3_stream(View in, View up, int cup, View out,
                                                      const bf16x8* __restrict__ frag,
                                                      const float* __restrict__ bias, View mask,
-                                                     int mode, int runs) {
+                                                     int mode, int runs,
+                                                     const float* __restrict__ head_w = nullptr,
+                                                     float* __restrict__ head_out = nullptr) {
     using G = ConvLds<CIN, COUT, RB, XB>;
     constexpr int NB = COUT / 16;
     constexpr int NQ = (27 * CIN + 31) / 32;
     constexpr int NCG = G::NCG, VOX = G::VOX, MT = G::MT, UNITS = G::UNITS, PER = G::PER;
     static_assert(CIN % 8 == 0 && COUT % 16 == 0, "channel blocking");
+    static_assert(KS == 1 || KS == 4, "split K over all four waves or none");
+    // tiles in a wave's products: its own MT, or all of the block's with KS = 4
+    constexpr int MP = KS == 1 ? MT : 4 * MT;
     __shared__ u32x4_t slab[4][UNITS];
     // Output staging: each wave's tiles as [tile][voxel][16 channels] bf16, so
     // that the stores to the channels-last output are 16 bytes per lane.
@@ -235,7 +182,7 @@ __global__ __launch_bounds__(256) void conv3_stream(View in, View up, int cup, V
         fromup[j] = UP && 8 * cg < cup;
         uoff[j] = !ok ? -1
                       : fromup[j] ? ((int64_t)(ys >> 1) * up.W + (xs >> 1)) * up.cs + up.c0 + 8 * cg
-                                  : ((int64_t)ys * W + xs) * in.cs + in.c0 + 8 * cg;
+                                  : ((int64_t)ys * W + xs) * in.cs + in.c0 + 8 * cg - (UP ? cup : 0);
     }
     const int64_t fstride = (int64_t)H * W * in.cs;
     const int64_t ustride = (int64_t)up.H * up.W * up.cs;
@@ -283,7 +230,7 @@ __global__ __launch_bounds__(256) void conv3_stream(View in, View up, int cup, V
     const int i = lane & 15, g = lane >> 4;
     // Weight fragments: held in registers for the whole run where they fit
     // (4 NQ NB registers), else re-read from L1 / L2 for every frame.
-    constexpr bool BREG = NQ * NB <= 42;
+    constexpr bool BREG = KS == 1 && NQ * NB <= 42;
     bf16x8 breg[BREG ? NQ : 1][NB];
     if constexpr (BREG) {
 #pragma unroll
@@ -295,43 +242,132 @@ __global__ __launch_bounds__(256) void conv3_stream(View in, View up, int cup, V
         u32x4_t next[PER];
         load_frame(t + 1 + PD, next);  // consumed after this frame's products (PD = 1)
                                        // or the next frame's (PD = 2)
-        f32x4 acc[MT][NB];
+        f32x4 acc[MP][NB];
 #pragma unroll
-        for (int m = 0; m < MT; ++m)
+        for (int m = 0; m < MP; ++m)
 #pragma unroll
             for (int n = 0; n < NB; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
-        // the lane's base in the slabs of frames t-1, t, t+1 (all loaded)
-        const int lane_off = (row * NCG + g) * VOX + v0 + i;
+        // the lane's base in the slabs of frames t-1, t, t+1 (all loaded): at
+        // the wave's first tile, or at the block's first with KS = 4; tile m
+        // of the products then sits at tile_off(m) units from it
+        const int lane_off = KS == 1 ? (row * NCG + g) * VOX + v0 + i : g * VOX + i;
+        auto tile_off = [](int m) {
+            return KS == 1 ? 16 * m : (m / G::TPR) * NCG * VOX + 16 * (m % G::TPR);
+        };
         const u32x4_t* fb[3] = {&slab[(t + 3) & 3][lane_off], &slab[t & 3][lane_off],
                                 &slab[(t + 1) & 3][lane_off]};
-        auto chunk = [&](auto qc, const bf16x8* bf) {
+        // A operands of chunk qc (one per tile) from the slabs, and the products
+        auto reada = [&](auto qc, bf16x8* a) {
             using C = ConvChunk<CIN, NCG, VOX, decltype(qc)::value>;
             const u32x4_t* sp =
                 (C::gs == 4 || g < C::gs) ? fb[C::fl] + C::ol : fb[C::fh] + C::oh;
 #pragma unroll
-            for (int m = 0; m < MT; ++m) {
-                const bf16x8 a = __builtin_bit_cast(bf16x8, sp[16 * m]);
+            for (int m = 0; m < MP; ++m) a[m] = __builtin_bit_cast(bf16x8, sp[tile_off(m)]);
+        };
+        auto mma = [&](const bf16x8* a, const bf16x8* bf) {
+#pragma unroll
+            for (int m = 0; m < MP; ++m)
 #pragma unroll
                 for (int n = 0; n < NB; ++n)
-                    acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bf[n], acc[m][n], 0, 0, 0);
-            }
+                    acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], bf[n], acc[m][n], 0, 0, 0);
         };
-        if constexpr (BREG) {
-            for_each_chunk([&](auto qc) { chunk(qc, breg[decltype(qc)::value]); },
-                           std::make_integer_sequence<int, NQ>{});
-        } else {
-            // re-read every frame, not hoisted out of the frame loop
-            const bf16x8* fr = frag;
-            asm volatile("" : "+s"(fr));
+        if constexpr (BREG && NQ * NB <= 14) {
+            // the smallest layer: four waves per SIMD hide the slab reads,
+            // which a read-ahead would cost (its registers allow three)
+            for_each_chunk(
+                [&](auto qc) {
+                    bf16x8 a[MP];
+                    reada(qc, a);
+                    mma(a, breg[decltype(qc)::value]);
+                },
+                std::make_integer_sequence<int, NQ>{});
+        } else if constexpr (BREG) {
+            // the slab reads of chunk q + 1 issued before chunk q's products
+            bf16x8 ab[2][MP];
+            reada(std::integral_constant<int, 0>{}, ab[0]);
             for_each_chunk(
                 [&](auto qc) {
                     constexpr int q = decltype(qc)::value;
-                    bf16x8 bf[NB];
-#pragma unroll
-                    for (int n = 0; n < NB; ++n) bf[n] = fr[(q * NB + n) * 64 + lane];
-                    chunk(qc, bf);
+                    if constexpr (q + 1 < NQ) reada(std::integral_constant<int, q + 1>{}, ab[(q + 1) & 1]);
+                    __builtin_amdgcn_sched_barrier(0);
+                    mma(ab[q & 1], breg[q]);
                 },
                 std::make_integer_sequence<int, NQ>{});
+        } else {
+            // re-read every frame, not hoisted out of the frame loop; the
+            // pointer is cast back to the global address space after the
+            // barrier, else the reads become flat loads, which the LDS
+            // counter also tracks, and every one of them waits for the slab
+            // reads in flight
+            const bf16x8* fp = frag;
+            asm volatile("" : "+s"(fp));
+            const __attribute__((address_space(1))) bf16x8* fr =
+                (const __attribute__((address_space(1))) bf16x8*)fp;
+            // The wave's chunks W, W + KS, ... as straight-line code in a
+            // software pipeline: step j issues the slab reads of chunk j + 1
+            // and the fragment loads of chunk j + D (a ring of D fragment sets
+            // in registers), then chunk j's products; the scheduling barrier
+            // keeps the compiler from sinking the loads back to their uses.
+            constexpr int D = NB <= 2 ? 4 : NB <= 4 ? 3 : 2;
+            auto run = [&](auto wc) {
+                constexpr int W = decltype(wc)::value;
+                constexpr int L = (NQ - W + KS - 1) / KS;
+                bf16x8 pf[D][NB];
+                bf16x8 ab[2][MP];
+                auto load = [&](bf16x8* dst, int q) {
+#pragma unroll
+                    for (int n = 0; n < NB; ++n) dst[n] = fr[(q * NB + n) * 64 + lane];
+                };
+                for_each_chunk(
+                    [&](auto jc) {
+                        constexpr int j = decltype(jc)::value;
+                        if constexpr (j < L) load(pf[j], W + KS * j);
+                    },
+                    std::make_integer_sequence<int, D>{});
+                reada(std::integral_constant<int, W>{}, ab[0]);
+                for_each_chunk(
+                    [&](auto jc) {
+                        constexpr int j = decltype(jc)::value;
+                        if constexpr (j + 1 < L)
+                            reada(std::integral_constant<int, W + KS * (j + 1)>{}, ab[(j + 1) & 1]);
+                        bf16x8 cur[NB];
+#pragma unroll
+                        for (int n = 0; n < NB; ++n) cur[n] = pf[j % D][n];
+                        if constexpr (j + D < L) load(pf[j % D], W + KS * (j + D));
+                        __builtin_amdgcn_sched_barrier(0);
+                        mma(ab[j & 1], cur);
+                    },
+                    std::make_integer_sequence<int, L>{});
+            };
+            if constexpr (KS == 1) {
+                run(std::integral_constant<int, 0>{});
+            } else {
+                switch (wave) {
+                    case 0: run(std::integral_constant<int, 0>{}); break;
+                    case 1: run(std::integral_constant<int, 1>{}); break;
+                    case 2: run(std::integral_constant<int, 2>{}); break;
+                    default: run(std::integral_constant<int, 3>{}); break;
+                }
+            }
+        }
+        if constexpr (KS > 1) {
+            // the four waves' partial sums of this wave's tiles, in wave order;
+            // red[wave][tile * NB + block of 16 channels][lane]
+            __shared__ f32x4 red[4][MP * NB][64];
+#pragma unroll
+            for (int m = 0; m < MP; ++m)
+#pragma unroll
+                for (int n = 0; n < NB; ++n) red[wave][m * NB + n][lane] = acc[m][n];
+            __syncthreads();
+#pragma unroll
+            for (int m = 0; m < MT; ++m)
+#pragma unroll
+                for (int n = 0; n < NB; ++n) {
+                    f32x4 sum = red[0][(tile0 + m) * NB + n][lane];
+#pragma unroll
+                    for (int k = 1; k < 4; ++k) sum += red[k][(tile0 + m) * NB + n][lane];
+                    acc[m][n] = sum;
+                }
         }
         // bias and ReLU in the accumulator layout (lane: channel i, voxels
         // 4 g .. 4 g + 3), through LDS into [voxel][channel], then 16-byte
@@ -351,7 +387,21 @@ __global__ __launch_bounds__(256) void conv3_stream(View in, View up, int cup, V
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        if (y < H) {
+        if constexpr (HEAD) {
+            static_assert(NB == 1 && MT * 16 <= 64, "head: 16 channels, a voxel per lane");
+            const int m = lane >> 4, vv = lane & 15;
+            const int xo = x0 + v0 + 16 * m + vv;
+            if (y < H && lane < MT * 16 && xo < W) {
+                const bf16x8 lo = load8(&obuf[wave][m][vv * 16]);
+                const bf16x8 hi = load8(&obuf[wave][m][vv * 16 + 8]);
+                float z = head_w[16];
+#pragma unroll
+                for (int c = 0; c < 8; ++c) z = fmaf(head_w[c], (float)lo[c], z);
+#pragma unroll
+                for (int c = 0; c < 8; ++c) z = fmaf(head_w[8 + c], (float)hi[c], z);
+                head_out[((int64_t)t * H + y) * W + xo] = softplus(z);
+            }
+        } else if (y < H) {
             const int64_t obase = ((int64_t)t * H + y) * W;
 #pragma unroll
             for (int c0 = 0; c0 < MT * NB * 32; c0 += 64) {
@@ -386,69 +436,131 @@ __global__ __launch_bounds__(256) void conv3_stream(View in, View up, int cup, V
     }
 }
 
-// First layer: one FP32 input channel, K = the 27 taps (one chunk of 32, the
-// last 5 zero).  Lane group g reads taps 8 g .. 8 g + 7 of its voxel.
+// First layer: one FP32 input channel, K = the 27 taps (one chunk of 32; the
+// weights of k = 27 .. 31 are zero).  Streamed like conv3_stream: a block
+// owns C1_RB rows x C1_XB voxels over a run of frames and keeps a ring of four
+// FP32 frame slabs ((C1_RB + 2) rows x (C1_XB + 2) voxels, zeros outside the
+// volume), the loads of frame t + 2 in registers during frame t.  Wave w
+// computes row w; lane group g reads taps 8 g .. 8 g + 7 of its voxel from the
+// slabs (a tap past the last reads the centre value, whose weight is zero).
+constexpr int C1_RB = 4, C1_XB = 64;
+
 template <int COUT>
-__global__ __launch_bounds__(64 * CONV_WAVES) void conv3_mfma_c1(const float* __restrict__ in,
-                                                                   View out,
-                                                                   const bf16x8* __restrict__ frag,
-                                                                   const float* __restrict__ bias) {
-    constexpr int NB = COUT / 16;
+__global__ __launch_bounds__(256) void conv3_c1_stream(const float* __restrict__ in, View out,
+                                                        const bf16x8* __restrict__ frag,
+                                                        const float* __restrict__ bias, int runs) {
+    constexpr int NB = COUT / 16, MT = C1_XB / 16;
+    constexpr int VOXS = C1_XB + 2, UNITS = (C1_RB + 2) * VOXS, SLOT = 512;
+    constexpr int PER = (UNITS + 255) / 256;
+    static_assert(UNITS <= SLOT && C1_RB == 4, "slab size, one row per wave");
+    __shared__ float slab[4 * SLOT];
+    __shared__ __bf16 obuf[4][MT * NB][16 * 16];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int T = out.T, H = out.H, W = out.W;
-    const int tiles_x = (W + 16 * CONV_MT - 1) / (16 * CONV_MT);
-    const int64_t wt = (int64_t)blockIdx.x * CONV_WAVES + wave;
-    if (wt >= (int64_t)T * H * tiles_x) return;
-    const int row = (int)(wt / tiles_x);
-    const int x0 = (int)(wt - (int64_t)row * tiles_x) * 16 * CONV_MT;
-    const int t = row / H, y = row - t * H;
-    const int i = lane & 15, g = lane >> 4;
-    // outputs staged per wave as [tile][voxel][16 channels] for 16-byte stores
-    __shared__ __bf16 obuf[CONV_WAVES][CONV_MT * NB][16 * 16];
-    bf16x8 b[NB];
+    const int tiles_x = (W + C1_XB - 1) / C1_XB;
+    const int rows_y = (H + C1_RB - 1) / C1_RB;
+    int b = blockIdx.x;
+    const int tx = b % tiles_x;
+    b /= tiles_x;
+    const int ty = b % rows_y;
+    const int run = b / rows_y;
+    const int ta = (int)((int64_t)T * run / runs), tb = (int)((int64_t)T * (run + 1) / runs);
+    const int x0 = tx * C1_XB, y0 = ty * C1_RB;
+
+    // this thread's slab units u = r * VOXS + v: offsets inside an input frame
+    int goff[PER];
 #pragma unroll
-    for (int n = 0; n < NB; ++n) b[n] = frag[n * 64 + lane];
+    for (int j = 0; j < PER; ++j) {
+        const int u = j * 256 + threadIdx.x;
+        const int r = u / VOXS, v = u - r * VOXS;
+        const int ys = y0 + r - 1, xs = x0 + v - 1;
+        goff[j] = (u < UNITS && ys >= 0 && ys < H && xs >= 0 && xs < W) ? ys * W + xs : -1;
+    }
+    const int64_t fstride = (int64_t)H * W;
+    auto load_frame = [&](int ts, float* reg) {
+        const bool tin = ts >= 0 && ts < T;
+        const float* fb = in + (tin ? (int64_t)ts * fstride : 0);
 #pragma unroll
-    for (int m = 0; m < CONV_MT; ++m) {
-        const int x = x0 + 16 * m + i;
-        bf16x8 a = zero8();
+        for (int j = 0; j < PER; ++j) reg[j] = (tin && goff[j] >= 0) ? fb[goff[j]] : 0.f;
+    };
+    auto store_slot = [&](int ts, const float* reg) {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int tap = 8 * g + e;
-            const int dt = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
-            const int ts = t + dt, ys = y + dy, xs = x + dx;
-            float v = 0.f;
-            if (tap < 27 && x < W && ts >= 0 && ts < T && ys >= 0 && ys < H && xs >= 0 && xs < W)
-                v = in[((int64_t)ts * H + ys) * W + xs];
-            a[e] = (__bf16)v;
+        for (int j = 0; j < PER; ++j) {
+            const int u = j * 256 + threadIdx.x;
+            if (u < UNITS) slab[(ts & 3) * SLOT + u] = reg[j];
         }
-        f32x4 acc[NB];
-#pragma unroll
-        for (int n = 0; n < NB; ++n)
-            acc[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[n], f32x4{0.f, 0.f, 0.f, 0.f},
-                                                             0, 0, 0);
-#pragma unroll
-        for (int n = 0; n < NB; ++n) {
-            const float bco = bias[16 * n + i];
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-                obuf[wave][m * NB + n][(4 * g + r) * 16 + i] = (__bf16)fmaxf(acc[n][r] + bco, 0.f);
+    };
+    {
+        float reg[PER];
+        for (int ts = ta - 1; ts <= ta + 1; ++ts) {
+            load_frame(ts, reg);
+            store_slot(ts, reg);
         }
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const int64_t obase = ((int64_t)t * H + y) * W;
+    float ahead[PER];
+    load_frame(ta + 2, ahead);
+    __syncthreads();
+
+    const int i = lane & 15, g = lane >> 4;
+    const int y = y0 + wave;
+    // the lane's taps: frame shift and offset inside a slab
+    int tdt[8], toff[8];
 #pragma unroll
-    for (int c0 = 0; c0 < CONV_MT * NB * 32; c0 += 64) {
-        const int c = c0 + lane;
-        const int tl = c >> 5, vv = (c & 31) >> 1, half = c & 1;
-        const int m = tl / NB, n = tl - m * NB;
-        const int xo = x0 + 16 * m + vv;
-        if (xo < W)
-            *reinterpret_cast<u32x4_t*>(out.p + (obase + xo) * out.cs + out.c0 + 16 * n + 8 * half) =
-                *reinterpret_cast<const u32x4_t*>(&obuf[wave][tl][vv * 16 + 8 * half]);
+    for (int e = 0; e < 8; ++e) {
+        const int tap = 8 * g + e;
+        const bool live = tap < 27;
+        const int dt = live ? tap / 9 - 1 : 0, dy = live ? (tap / 3) % 3 - 1 : 0,
+                  dx = live ? tap % 3 - 1 : 0;
+        tdt[e] = dt;
+        toff[e] = (wave + 1 + dy) * VOXS + 1 + dx + i;
+    }
+    bf16x8 breg[NB];
+#pragma unroll
+    for (int n = 0; n < NB; ++n) breg[n] = frag[n * 64 + lane];
+    for (int t = ta; t < tb; ++t) {
+        float next[PER];
+        load_frame(t + 3, next);
+        int base[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) base[e] = ((t + tdt[e]) & 3) * SLOT + toff[e];
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            bf16x8 a;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) a[e] = (__bf16)slab[base[e] + 16 * m];
+#pragma unroll
+            for (int n = 0; n < NB; ++n) {
+                const f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                    a, breg[n], f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+                const float bco = bias[16 * n + i];
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    obuf[wave][m * NB + n][(4 * g + r) * 16 + i] = (__bf16)fmaxf(acc[r] + bco, 0.f);
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (y < H) {
+            const int64_t obase = ((int64_t)t * H + y) * W;
+#pragma unroll
+            for (int c0 = 0; c0 < MT * NB * 32; c0 += 64) {
+                const int c = c0 + lane;
+                const int tl = c >> 5, vv = (c & 31) >> 1, half = c & 1;
+                const int m = tl / NB, n = tl - m * NB;
+                const int xo = x0 + 16 * m + vv;
+                if (xo < W)
+                    *reinterpret_cast<u32x4_t*>(out.p + (obase + xo) * out.cs + out.c0 + 16 * n +
+                                                8 * half) =
+                        *reinterpret_cast<const u32x4_t*>(&obuf[wave][tl][vv * 16 + 8 * half]);
+            }
+        }
+        // slot of frame t - 2, read by no one now
+        store_slot(t + 2, ahead);
+#pragma unroll
+        for (int j = 0; j < PER; ++j) ahead[j] = next[j];
+        __syncthreads();
     }
 }
 
@@ -713,8 +825,6 @@ __global__ void up2_bwd(View gout, View act, View gin, int C) {
 // ---------------------------------------------------------------------------
 // Head (1x1x1 conv, softplus), loss and their gradients
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ float softplus(float z) { return z > 20.f ? z : log1pf(expf(z)); }
-
 // z[v] = sum_c wh[c] d1[v][c] + bh;  xh[v] = softplus(z[v]).
 __global__ void head_fwd(View d1, const float* __restrict__ wh, float* __restrict__ z,
                          float* __restrict__ xh) {

@@ -47,6 +47,28 @@ def test_forward_matches_oracle(shape):
     assert err <= 3e-2
 
 
+@pytest.mark.parametrize("shape", [(5, 13, 37), (3, 20, 70), (7, 9, 130), (9, 70, 200)])
+def test_inference_forward_equals_the_training_forward(shape):
+    """The inference network fuses what training keeps apart (the upsampled
+    half of the last concatenation read at the parent voxels, the head in the
+    last convolution's epilogue, the first layer reading S without a copy,
+    the skip tensor on its own); on the same weights and input it gives the
+    training network's output bit for bit.  Shapes with ragged row and voxel
+    tiles, several tiles of the first layer, and odd sizes at every level."""
+    params = U.init_params(23)
+    r = np.random.Generator(np.random.PCG64(24))
+    S = _t(r.random(shape))
+    with UNet(shape) as a, UNet(shape, training=True) as b:
+        a.set_params(U.pack(params))
+        b.set_params(U.pack(params))
+        x_inf = a.forward(S).cpu().numpy()
+        x_tr = b.forward(S).cpu().numpy()
+    d = float(np.max(np.abs(x_inf - x_tr)))
+    print(f"inference vs training {shape}: max |diff| {d:.3e}", flush=True)
+    assert np.all(np.isfinite(x_inf)) and np.all(x_inf > 0)
+    assert np.array_equal(x_inf, x_tr)
+
+
 @pytest.mark.parametrize("shape", [(5, 13, 37), (6, 24, 40)])
 def test_gradients_match_oracle(shape):
     params = U.init_params(31)
