@@ -391,10 +391,10 @@ int64_t sfseg_unet_param_count(void);
 /* Create a network (weights zero until sfseg_unet_set_params).  training != 0
  * also allocates gradient buffers and the activations that the backward pass
  * reads; an inference network (training = 0) reads S in its first layer,
- * forms the upsampled half of the last skip concatenation while its
- * convolution stages its input, and runs the head in the last convolution,
- * so it holds neither (same output bit for bit, 108 bytes per voxel less
- * memory).  SFSEG_ERR_INVALID_ARG for sizes < 1 or
+ * forms the upsampled halves of the skip concatenations while the
+ * convolutions stage their inputs, and runs the head in the last
+ * convolution, so it holds neither (same output bit for bit, 124 bytes per
+ * voxel less memory).  SFSEG_ERR_INVALID_ARG for sizes < 1 or
  * max_T * max_H * max_W * 48 >= 2^31; SFSEG_ERR_OOM / SFSEG_ERR_HIP. */
 int sfseg_unet_create(int32_t max_T, int32_t max_H, int32_t max_W, int32_t training, void *stream,
                       sfseg_unet **out);

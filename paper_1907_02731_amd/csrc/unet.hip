@@ -127,9 +127,9 @@ hipError_t conv_fwd_up(int cin, int cout, View in, View up, int cup, View out,
         const int64_t tiles = (int64_t)((out.H + RB - 1) / RB) * ((out.W + XB - 1) / XB);         \
         const int runs = conv_runs(tiles, out.T);                                                 \
         if (up.p)                                                                                 \
-            hipLaunchKernelGGL((conv3_stream<CI, CO, RB, XB, true>), dim3((unsigned)(tiles * runs)), \
-                               dim3(256), 0, s, in, up, cup, out, frag, bias, mask, mode, runs,   \
-                               nullptr, nullptr);                                                 \
+            hipLaunchKernelGGL((conv3_stream<CI, CO, RB, XB, true, false, KS>),                   \
+                               dim3((unsigned)(tiles * runs)), dim3(256), 0, s, in, up, cup, out, \
+                               frag, bias, mask, mode, runs, nullptr, nullptr);                   \
         else                                                                                      \
             hipLaunchKernelGGL((conv3_stream<CI, CO, RB, XB, false, false, KS>),                  \
                                dim3((unsigned)(tiles * runs)), dim3(256), 0, s, in, up, cup, out, \
@@ -303,13 +303,13 @@ int sfseg_unet_create(int32_t max_T, int32_t max_H, int32_t max_W, int32_t train
         }
         if (rc) break;
         // Inference keeps only what the forward pass reads: the first layer
-        // reads S itself, the full-resolution skip tensor has its 16 channels
-        // alone (the upsampled half of the concatenation is never formed) and
-        // the head is fused into the last convolution.
-        const int64_t cat1_ch = n->training ? 48 : 16;
+        // reads S itself, the skip tensors have their own channels alone (the
+        // upsampled halves of the concatenations are never formed) and the
+        // head is fused into the last convolution.
+        const int64_t cat1_ch = n->training ? 48 : 16, cat2_ch = n->training ? 96 : 32;
         if ((rc = dalloc(n, &n->e1a, nfull * 16)) || (rc = dalloc(n, &n->cat1, nfull * cat1_ch)) ||
             (rc = dalloc(n, &n->p1, nh * 16)) || (rc = dalloc(n, &n->e2a, nh * 32)) ||
-            (rc = dalloc(n, &n->cat2, nh * 96)) || (rc = dalloc(n, &n->p2, nq * 32)) ||
+            (rc = dalloc(n, &n->cat2, nh * cat2_ch)) || (rc = dalloc(n, &n->p2, nq * 32)) ||
             (rc = dalloc(n, &n->ba, nq * 64)) || (rc = dalloc(n, &n->bb, nq * 64)) ||
             (rc = dalloc(n, &n->d2a, nh * 32)) || (rc = dalloc(n, &n->d2, nh * 32)) ||
             (rc = dalloc(n, &n->d1a, nfull * 16)))
@@ -409,13 +409,14 @@ int sfseg_unet_forward(sfseg_unet* n, const float* S, int32_t T, int32_t H, int3
     const bool tr = n->training != 0;
     if (tr) HIP_TRY(hipMemcpyAsync(n->in32, S, sizeof(float) * nv, hipMemcpyDeviceToDevice, s));
     const View none{nullptr, 0, 0, 0, 0, 0};
-    // e1: channels 32..47 of the concatenation in training, its own
-    // 16-channel tensor in inference
+    // the skip tensors e1, e2: the last channels of the concatenations in
+    // training, tensors of their own in inference
     const View e1a = view(n->e1a, T, H, W, 16, 0),
                e1 = tr ? view(n->cat1, T, H, W, 48, 32) : view(n->cat1, T, H, W, 16, 0),
                cat1 = view(n->cat1, T, H, W, 48, 0), u1 = view(n->cat1, T, H, W, 48, 0),
                p1 = view(n->p1, Th, Hh, Wh, 16, 0), e2a = view(n->e2a, Th, Hh, Wh, 32, 0),
-               e2 = view(n->cat2, Th, Hh, Wh, 96, 64), cat2 = view(n->cat2, Th, Hh, Wh, 96, 0),
+               e2 = tr ? view(n->cat2, Th, Hh, Wh, 96, 64) : view(n->cat2, Th, Hh, Wh, 32, 0),
+               cat2 = view(n->cat2, Th, Hh, Wh, 96, 0),
                u2 = view(n->cat2, Th, Hh, Wh, 96, 0), p2 = view(n->p2, Tq, Hq, Wq, 32, 0),
                ba = view(n->ba, Tq, Hq, Wq, 64, 0), bb = view(n->bb, Tq, Hq, Wq, 64, 0),
                d2a = view(n->d2a, Th, Hh, Wh, 32, 0), d2 = view(n->d2, Th, Hh, Wh, 32, 0),
@@ -434,10 +435,16 @@ int sfseg_unet_forward(sfseg_unet* n, const float* S, int32_t T, int32_t H, int3
     HIP_TRY(hipGetLastError());
     HIP_TRY(conv_fwd(32, 64, p2, ba, n->ffwd[BOTA], bias(BOTA), none, 0, s));
     HIP_TRY(conv_fwd(64, 64, ba, bb, n->ffwd[BOTB], bias(BOTB), none, 0, s));
-    hipLaunchKernelGGL(sfseg::unet::up2_fwd, dim3(grid_for((int64_t)Th * Hh * Wh * 8)), dim3(256), 0,
-                       s, bb, u2, 64);
-    HIP_TRY(hipGetLastError());
-    HIP_TRY(conv_fwd(96, 32, cat2, d2a, n->ffwd[DEC2A], bias(DEC2A), none, 0, s));
+    if (tr) {
+        hipLaunchKernelGGL(sfseg::unet::up2_fwd, dim3(grid_for((int64_t)Th * Hh * Wh * 8)), dim3(256),
+                           0, s, bb, u2, 64);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(conv_fwd(96, 32, cat2, d2a, n->ffwd[DEC2A], bias(DEC2A), none, 0, s));
+    } else {
+        // the upsampled half of the concatenation read at the parent voxels
+        // while the convolution stages its input
+        HIP_TRY(conv_fwd_up(96, 32, e2, bb, 64, d2a, n->ffwd[DEC2A], bias(DEC2A), none, 0, s));
+    }
     HIP_TRY(conv_fwd(32, 32, d2a, d2, n->ffwd[DEC2B], bias(DEC2B), none, 0, s));
     if (tr) {
         // the backward pass reads the concatenation, d1 and z
@@ -450,10 +457,8 @@ int sfseg_unet_forward(sfseg_unet* n, const float* S, int32_t T, int32_t H, int3
         HIP_TRY(hipGetLastError());
         HIP_TRY(hipMemcpyAsync(out, n->xh, sizeof(float) * nv, hipMemcpyDeviceToDevice, s));
     } else {
-        // the upsampled half of the concatenation is read at the parent voxels
-        // while the convolution stages its input (at half resolution the
-        // separate upsampling is the cheaper of the two), and the head runs
-        // in the last convolution's epilogue
+        // the same at full resolution, and the head in the last
+        // convolution's epilogue
         HIP_TRY(conv_fwd_up(48, 16, e1, d2, 32, d1a, n->ffwd[DEC1A], bias(DEC1A), none, 0, s));
         HIP_TRY(conv_fwd_head(d1a, d1a, n->ffwd[DEC1B], bias(DEC1B), w + layer_offset(HEAD), out, s));
     }
