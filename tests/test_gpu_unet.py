@@ -47,7 +47,8 @@ def test_forward_matches_oracle(shape):
     assert err <= 3e-2
 
 
-@pytest.mark.parametrize("shape", [(5, 13, 37), (3, 20, 70), (7, 9, 130), (9, 70, 200)])
+@pytest.mark.parametrize("shape", [(1, 1, 1), (2, 3, 5), (5, 13, 37), (3, 20, 70), (7, 9, 130),
+                                   (9, 70, 200)])
 def test_inference_forward_equals_the_training_forward(shape):
     """The inference network fuses what training keeps apart (the upsampled
     half of the last concatenation read at the parent voxels, the head in the
