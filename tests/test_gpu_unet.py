@@ -70,6 +70,26 @@ def test_inference_forward_equals_the_training_forward(shape):
     assert np.array_equal(x_inf, x_tr)
 
 
+@pytest.mark.parametrize("training", [False, True])
+def test_forward_in_place_and_in_a_larger_network(training):
+    """S and out may be the same buffer (the first kernel reads S, the last
+    writes out), and a network sized for a larger volume gives the same
+    output, bit for bit, on a smaller one."""
+    shape = (5, 13, 37)
+    params = U.pack(U.init_params(25))
+    S = np.random.Generator(np.random.PCG64(26)).random(shape)
+    with UNet(shape, training=training) as a, UNet((9, 40, 96), training=training) as b:
+        a.set_params(params)
+        b.set_params(params)
+        ref = a.forward(_t(S)).cpu().numpy()
+        buf = _t(S)
+        a.forward(buf, out=buf)
+        big = b.forward(_t(S)).cpu().numpy()
+        inplace = buf.cpu().numpy()
+    assert np.array_equal(inplace, ref)
+    assert np.array_equal(big, ref)
+
+
 @pytest.mark.parametrize("shape", [(5, 13, 37), (6, 24, 40)])
 def test_gradients_match_oracle(shape):
     params = U.init_params(31)
